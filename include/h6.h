@@ -1,0 +1,248 @@
+/*
+ * h6.h -- C ABI of libh6, a 6th-order Hermite direct N-body library for one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the paper's statement of the method (Goz et al.,
+ * "Direct N-body code on low-power embedded ARM GPUs"):
+ *   - Sec. 3, the three stages of the 6th-order Hermite scheme: predict
+ *     (h6_predict), evaluate acceleration, jerk and snap (h6_evaluate),
+ *     correct (h6_correct);
+ *   - Sec. 3 item 3: the time step (generalized Aarseth criterion, inside
+ *     h6_correct / h6_initial_steps), energy and angular momentum
+ *     (h6_energy) computed on the device;
+ *   - Sec. 3 item 4 (kernel steps i-iv): the evaluation stages source
+ *     particles through on-chip local memory and skips the self term;
+ *   - Sec. 3 item 6: precision is selectable (H6_FP64, H6_MIXED);
+ *   - Sec. 2: block time stepping (h6_next_block and the power-of-two
+ *     step rule in h6_correct).
+ *
+ * Conventions shared by every call:
+ *   - Particle data lives in caller-owned DEVICE memory as structure of
+ *     arrays: one contiguous double array per vector component. The
+ *     library never frees caller memory. A context owns only its scratch
+ *     (partial sums, scheduler and reduction buffers), sized at creation.
+ *   - Times and steps are int64 counts of ticks of 2^-H6_TICK_BITS time
+ *     units; block steps are powers of two, level L meaning 2^-L.
+ *   - Every call enqueues work on the context's HIP stream and returns
+ *     without waiting, except those marked "synchronizes".
+ *   - Errors are negative return codes; nothing aborts or throws. Arguments
+ *     are validated before any HIP call. A HIP failure returns H6_EHIP
+ *     and its text is kept for h6_last_error. A context is not
+ *     thread-safe; distinct contexts are independent.
+ *   - Softening is Plummer: the pair potential is -m / sqrt(r^2 + eps^2).
+ *     With eps > 0 the self term is exactly zero; with eps == 0 it is
+ *     skipped explicitly (particles must then never coincide).
+ */
+#ifndef H6_H
+#define H6_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define H6_TICK_BITS 40
+
+/* Return codes. */
+enum {
+    H6_OK = 0,
+    H6_EINVAL = -1,     /* bad argument: null pointer, size out of range */
+    H6_ENOMEM = -2,     /* device scratch allocation failed */
+    H6_EHIP = -3,       /* a HIP runtime call failed; see h6_last_error */
+    H6_ESTATE = -4,     /* call not valid in the context's current state */
+    H6_EDTMIN = -5,     /* a step fell below 2^-lev_max (step clamped) */
+    H6_ENONFINITE = -6  /* a corrected quantity was not finite */
+};
+
+/* Evaluation arithmetic (Sec. 3 item 6). */
+enum {
+    H6_FP64 = 0,  /* all pair arithmetic and sums in IEEE double */
+    H6_MIXED = 1  /* double differences and accumulators, float pair math */
+};
+
+typedef struct h6_ctx_s *h6_ctx;
+
+/* Integrator state: device arrays of length n (caller-owned). */
+typedef struct {
+    double *x[3], *v[3];        /* position, velocity at time t */
+    double *a[3], *j[3], *s[3]; /* acceleration, jerk, snap at t */
+    double *c[3];               /* crackle at t (start-up or interpolated) */
+    double *m;                  /* masses */
+    int64_t *t;                 /* particle time, ticks */
+    int64_t *dt;                /* particle step, ticks (power of two) */
+} h6_state;
+
+/* Predicted sources: device arrays of length n (caller-owned). */
+typedef struct {
+    double *x[3], *v[3], *a[3];
+} h6_pred;
+
+/* Evaluated acceleration, jerk, snap: device arrays of length n_act. */
+typedef struct {
+    double *a[3], *j[3], *s[3];
+} h6_force;
+
+/* Block-step parameters. */
+typedef struct {
+    double eta;    /* accuracy parameter of the 6th-order criterion */
+    int lev_min;   /* largest step 2^-lev_min */
+    int lev_max;   /* smallest step 2^-lev_max (below: H6_EDTMIN) */
+    int precision; /* H6_FP64 or H6_MIXED for the evaluation */
+} h6_params;
+
+/* Counters filled by h6_run_blocks. */
+typedef struct {
+    int64_t blocks;       /* block steps taken */
+    int64_t particle_steps; /* sum of active counts */
+    double interactions;  /* sum over blocks of n_act * n (self pair counted) */
+    int64_t t_end;        /* time reached, ticks */
+} h6_run_stats;
+
+/*
+ * Create a context for systems of up to n_max particles with softening
+ * length eps (>= 0). hip_stream is a hipStream_t (NULL: the null stream).
+ * Allocates the scratch buffers on the current device.
+ * Errors: H6_EINVAL (n_max < 1, eps < 0 or not finite, ctx NULL),
+ * H6_ENOMEM, H6_EHIP.
+ */
+int h6_create(h6_ctx *ctx, int64_t n_max, double eps, void *hip_stream);
+
+/* Free the context's scratch and the context. NULL is accepted. */
+int h6_destroy(h6_ctx ctx);
+
+/* Change the stream later calls enqueue on. */
+int h6_set_stream(h6_ctx ctx, void *hip_stream);
+
+/*
+ * Launch shape of the evaluation kernels: threads per workgroup (64, 128
+ * or 256), targets per thread (1 or 2) and number of source slices the
+ * sum is split into (>= 1). 0 keeps the built-in choice for that field.
+ * Results agree to rounding for every shape. Errors: H6_EINVAL.
+ */
+int h6_set_eval_config(h6_ctx ctx, int block, int ipl, int n_split);
+
+/*
+ * Predictor (Sec. 3, first stage): Taylor prediction of all n particles to
+ * time t_tick, each over its own interval t_tick - t[i]: position to 5th
+ * order, velocity to 4th, acceleration to 3rd, from the stored a, j, s, c.
+ * h6_predict_dt predicts every particle over the same interval dt (shared
+ * steps; the state's t is not read).
+ * Errors: H6_EINVAL (null pointer, n < 1 or n > n_max).
+ */
+int h6_predict(h6_ctx ctx, const h6_state *st, int64_t n, int64_t t_tick,
+               const h6_pred *out);
+int h6_predict_dt(h6_ctx ctx, const h6_state *st, int64_t n, double dt,
+                  const h6_pred *out);
+
+/*
+ * Evaluation (Sec. 3, second stage, and kernel steps i-iv): for each target
+ * k < n_act, particle i = active[k] (active may be NULL: i = k), the sums
+ * over every source j != i of the softened acceleration, jerk and snap
+ * from the predicted x, v, a and masses m of all n particles. Results go to
+ * out at index k. precision is H6_FP64 or H6_MIXED. n_act == 0 is a no-op.
+ * Errors: H6_EINVAL (null pointer, n < 1, n > n_max, n_act < 0 or
+ * n_act > n_max, bad precision). Active indices must lie in [0, n); they
+ * are not checked on the device.
+ */
+int h6_evaluate(h6_ctx ctx, const h6_pred *src, const double *m, int64_t n,
+                const int32_t *active, int64_t n_act, int precision,
+                const h6_force *out);
+
+/*
+ * Corrector (Sec. 3, third stage) for a block: each active particle
+ * i = active[k] is due at t_next = t[i] + dt[i]. Its x, v are corrected
+ * to 6th order from a, j, s at both ends of the step (old ones in st,
+ * new ones in f[k]); crackle, pop and the 5th derivative at t_next come
+ * from the quintic interpolant; the new step is the largest power of two
+ * not above the generalized Aarseth criterion
+ *   eta [(|a||s| + |j|^2) / (|c||a5| + |p|^2)]^(1/6),
+ * at least lev_min, shrinking freely but growing by one level only when
+ * t_next is a multiple of twice the old step. a, j, s, c, t, dt are
+ * updated. Steps below 2^-lev_max and non-finite results raise flags read
+ * by h6_check_status.
+ * Errors: H6_EINVAL.
+ */
+int h6_correct(h6_ctx ctx, h6_state *st, const int32_t *active,
+               int64_t n_act, const h6_force *f, int64_t t_next,
+               const h6_params *prm);
+
+/* Shared-step corrector: all n particles over the same step dt; t and dt
+ * of the state are left untouched. Errors: H6_EINVAL. */
+int h6_correct_shared(h6_ctx ctx, h6_state *st, int64_t n,
+                      const h6_force *f, double dt);
+
+/*
+ * Start-up at t = 0, where no snap or crackle exist yet: pass 1 evaluates
+ * a and j from x, v; pass 2 evaluates s and the pairwise crackle c with
+ * the pass-1 a and j of every source. Writes a, j, s, c of the state.
+ * Errors: H6_EINVAL.
+ */
+int h6_init_forces(h6_ctx ctx, h6_state *st, int64_t n);
+
+/*
+ * Initial steps: t = 0 and dt = the largest power of two not above the
+ * start-up (4th-order) criterion eta_s [(|a||s|+|j|^2)/(|j||c|+|s|^2)]^(1/2),
+ * between 2^-lev_max and 2^-lev_min. Errors: H6_EINVAL.
+ */
+int h6_initial_steps(h6_ctx ctx, h6_state *st, int64_t n, double eta_s,
+                     int lev_min, int lev_max);
+
+/*
+ * Block scheduler (synchronizes): t_next = min_i (t[i] + dt[i]) and the
+ * particles due at t_next, written to active (device, length >= n) in
+ * increasing index order; *t_next and *n_act are host outputs.
+ * Errors: H6_EINVAL, H6_EHIP.
+ */
+int h6_next_block(h6_ctx ctx, const h6_state *st, int64_t n,
+                  int32_t *active, int64_t *t_next, int64_t *n_act);
+
+/*
+ * One whole block step (synchronizes): h6_next_block, h6_predict of all
+ * particles, h6_evaluate of the active ones, h6_correct. pred (length n)
+ * and f, active (length >= n) are caller-owned work arrays.
+ * Errors: as the calls it makes, plus the device flags (H6_EDTMIN,
+ * H6_ENONFINITE) checked after the step.
+ */
+int h6_block_step(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred,
+                  const h6_force *f, int32_t *active, const h6_params *prm,
+                  int64_t *t_next, int64_t *n_act);
+
+/*
+ * Block steps until every particle reaches t_end (ticks, a multiple of
+ * 2^-lev_min; synchronizes once per block). stats may be NULL.
+ * Errors: as h6_block_step; H6_EINVAL if some t[i] > t_end.
+ */
+int h6_run_blocks(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred,
+                  const h6_force *f, int32_t *active, const h6_params *prm,
+                  int64_t t_end, h6_run_stats *stats);
+
+/* nsteps shared steps of length dt over all n particles (asynchronous). */
+int h6_shared_steps(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred,
+                    const h6_force *f, double dt, int64_t nsteps,
+                    int precision);
+
+/*
+ * Energy and angular momentum (synchronizes; Sec. 3 item 3 and Eq. (1)):
+ * out[0] kinetic energy, out[1] potential energy
+ * -sum_{i<j} m_i m_j / sqrt(r_ij^2 + eps^2), out[2..4] angular momentum
+ * sum m x cross v. Only meaningful when all particles share one time.
+ * Errors: H6_EINVAL, H6_EHIP.
+ */
+int h6_energy(h6_ctx ctx, const h6_state *st, int64_t n, double out[5]);
+
+/*
+ * Device status flags raised since the last call (synchronizes), then
+ * cleared: H6_OK, H6_EDTMIN or H6_ENONFINITE.
+ */
+int h6_check_status(h6_ctx ctx);
+
+/* Text of a return code; text of the context's last failure ("" if none). */
+const char *h6_strerror(int code);
+const char *h6_last_error(h6_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* H6_H */

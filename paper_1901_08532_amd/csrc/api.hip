@@ -1,0 +1,400 @@
+// C ABI of libh6: argument validation, scratch ownership, error mapping,
+// and the native block-step driver loop. Kernels live in eval.hip and
+// steps.hip; this file only validates, allocates and sequences.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "h6_internal.h"
+
+using namespace h6;
+
+namespace {
+
+int fail_hip(h6_ctx ctx, hipError_t e, const char *what) {
+    if (ctx) {
+        char buf[256];
+        std::snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+        ctx->last_error = buf;
+    }
+    return H6_EHIP;
+}
+
+int fail_arg(h6_ctx ctx, const char *what) {
+    if (ctx) ctx->last_error = what;
+    return H6_EINVAL;
+}
+
+#define H6_TRY(ctx, call, what)                            \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return fail_hip(ctx, e_, what); \
+    } while (0)
+
+bool state_ok(const h6_state *st, bool need_time) {
+    if (!st || !st->m) return false;
+    for (int c = 0; c < 3; ++c)
+        if (!st->x[c] || !st->v[c] || !st->a[c] || !st->j[c] || !st->s[c] || !st->c[c]) return false;
+    if (need_time && (!st->t || !st->dt)) return false;
+    return true;
+}
+
+bool pred_ok(const h6_pred *p) {
+    if (!p) return false;
+    for (int c = 0; c < 3; ++c)
+        if (!p->x[c] || !p->v[c] || !p->a[c]) return false;
+    return true;
+}
+
+bool force_ok(const h6_force *f) {
+    if (!f) return false;
+    for (int c = 0; c < 3; ++c)
+        if (!f->a[c] || !f->j[c] || !f->s[c]) return false;
+    return true;
+}
+
+bool params_ok(const h6_params *p) {
+    return p && std::isfinite(p->eta) && p->eta > 0.0 && p->lev_min >= 0 &&
+           p->lev_max >= p->lev_min && p->lev_max <= kTickBits &&
+           (p->precision == H6_FP64 || p->precision == H6_MIXED);
+}
+
+int check_n(h6_ctx ctx, int64_t n) {
+    if (n < 1 || n > ctx->n_max) return fail_arg(ctx, "particle count out of range");
+    return H6_OK;
+}
+
+SrcPtrs src_from_pred(const h6_pred *p, const double *m) {
+    SrcPtrs s;
+    for (int c = 0; c < 3; ++c) {
+        s.x[c] = p->x[c];
+        s.v[c] = p->v[c];
+        s.a[c] = p->a[c];
+        s.j[c] = nullptr;
+    }
+    s.m = m;
+    return s;
+}
+
+OutPtrs out_from_force(const h6_force *f) {
+    OutPtrs o;
+    for (int c = 0; c < 12; ++c) o.p[c] = nullptr;
+    for (int c = 0; c < 3; ++c) {
+        o.p[c] = f->a[c];
+        o.p[3 + c] = f->j[c];
+        o.p[6 + c] = f->s[c];
+    }
+    return o;
+}
+
+int read_flags(h6_ctx ctx) {
+    int32_t *h = (int32_t *)ctx->host;
+    H6_TRY(ctx, hipMemcpyAsync(h, ctx->flags, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream),
+           "flag readback");
+    H6_TRY(ctx, hipMemsetAsync(ctx->flags, 0, sizeof(int32_t), ctx->stream), "flag reset");
+    H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    if (h[0] & kFlagNonFinite) return H6_ENONFINITE;
+    if (h[0] & kFlagDtMin) return H6_EDTMIN;
+    return H6_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *h6_strerror(int code) {
+    switch (code) {
+        case H6_OK: return "ok";
+        case H6_EINVAL: return "invalid argument";
+        case H6_ENOMEM: return "out of device memory";
+        case H6_EHIP: return "HIP runtime error";
+        case H6_ESTATE: return "invalid state";
+        case H6_EDTMIN: return "time step below 2^-lev_max";
+        case H6_ENONFINITE: return "non-finite result";
+        default: return "unknown error";
+    }
+}
+
+const char *h6_last_error(h6_ctx ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+int h6_create(h6_ctx *out, int64_t n_max, double eps, void *hip_stream) {
+    if (!out) return H6_EINVAL;
+    *out = nullptr;
+    if (n_max < 1 || n_max > kMaxParticles || !std::isfinite(eps) || eps < 0.0) return H6_EINVAL;
+    h6_ctx ctx = new (std::nothrow) h6_ctx_s;
+    if (!ctx) return H6_ENOMEM;
+    ctx->n_max = n_max;
+    ctx->eps = eps;
+    ctx->eps2 = eps * eps;
+    ctx->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipGetDevice(&ctx->device);
+    if (e != hipSuccess) {
+        delete ctx;
+        return H6_EHIP;
+    }
+    // partial sums: n_split * ncomp * n_act doubles, n_split * n_act <= cap
+    const int64_t cap_pairs = std::max<int64_t>(2 * n_max, (int64_t)1 << 21);
+    ctx->partial_cap = 9 * cap_pairs;
+    ctx->sched_blocks = sched_blocks_for(n_max);
+    const int64_t eb = energy_blocks_for(n_max);
+    bool ok = hipMalloc(&ctx->partial, sizeof(double) * ctx->partial_cap) == hipSuccess &&
+              hipMalloc(&ctx->sched64, sizeof(int64_t) * (2 + ctx->sched_blocks)) == hipSuccess &&
+              hipMalloc(&ctx->sched32, sizeof(int32_t) * (1 + 2 * ctx->sched_blocks)) == hipSuccess &&
+              hipMalloc(&ctx->counters, sizeof(unsigned) * 8) == hipSuccess &&
+              hipMalloc(&ctx->flags, sizeof(int32_t) * 4) == hipSuccess &&
+              hipMalloc(&ctx->ered, sizeof(double) * (8 + 10 * eb)) == hipSuccess &&
+              hipHostMalloc(&ctx->host, 256, hipHostMallocDefault) == hipSuccess;
+    if (ok) {
+        ok = hipMemset(ctx->counters, 0, sizeof(unsigned) * 8) == hipSuccess &&
+             hipMemset(ctx->flags, 0, sizeof(int32_t) * 4) == hipSuccess &&
+             hipDeviceSynchronize() == hipSuccess;
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        h6_destroy(ctx);
+        return H6_ENOMEM;
+    }
+    *out = ctx;
+    return H6_OK;
+}
+
+int h6_destroy(h6_ctx ctx) {
+    if (!ctx) return H6_OK;
+    if (ctx->partial || ctx->sched64) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->partial) (void)hipFree(ctx->partial);
+    if (ctx->sched64) (void)hipFree(ctx->sched64);
+    if (ctx->sched32) (void)hipFree(ctx->sched32);
+    if (ctx->counters) (void)hipFree(ctx->counters);
+    if (ctx->flags) (void)hipFree(ctx->flags);
+    if (ctx->ered) (void)hipFree(ctx->ered);
+    if (ctx->host) (void)hipHostFree(ctx->host);
+    delete ctx;
+    return H6_OK;
+}
+
+int h6_set_stream(h6_ctx ctx, void *hip_stream) {
+    if (!ctx) return H6_EINVAL;
+    ctx->stream = (hipStream_t)hip_stream;
+    return H6_OK;
+}
+
+int h6_set_eval_config(h6_ctx ctx, int block, int ipl, int n_split) {
+    if (!ctx) return H6_EINVAL;
+    if (block != 0 && block != 64 && block != 128 && block != 256)
+        return fail_arg(ctx, "block must be 0, 64, 128 or 256");
+    if (ipl != 0 && ipl != 1 && ipl != 2) return fail_arg(ctx, "ipl must be 0, 1 or 2");
+    if (n_split < 0) return fail_arg(ctx, "n_split must be >= 0");
+    ctx->cfg_block = block;
+    ctx->cfg_ipl = ipl;
+    ctx->cfg_split = n_split;
+    return H6_OK;
+}
+
+int h6_predict(h6_ctx ctx, const h6_state *st, int64_t n, int64_t t_tick, const h6_pred *out) {
+    if (!ctx) return H6_EINVAL;
+    if (!state_ok(st, true) || !pred_ok(out)) return fail_arg(ctx, "null array");
+    if (int rc = check_n(ctx, n)) return rc;
+    H6_TRY(ctx, launch_predict(ctx, st, (int)n, t_tick, 0.0, false, out), "predict");
+    return H6_OK;
+}
+
+int h6_predict_dt(h6_ctx ctx, const h6_state *st, int64_t n, double dt, const h6_pred *out) {
+    if (!ctx) return H6_EINVAL;
+    if (!state_ok(st, false) || !pred_ok(out)) return fail_arg(ctx, "null array");
+    if (int rc = check_n(ctx, n)) return rc;
+    if (!std::isfinite(dt)) return fail_arg(ctx, "dt not finite");
+    H6_TRY(ctx, launch_predict(ctx, st, (int)n, 0, dt, true, out), "predict");
+    return H6_OK;
+}
+
+int h6_evaluate(h6_ctx ctx, const h6_pred *src, const double *m, int64_t n, const int32_t *active,
+                int64_t n_act, int precision, const h6_force *out) {
+    if (!ctx) return H6_EINVAL;
+    if (!pred_ok(src) || !m || !force_ok(out)) return fail_arg(ctx, "null array");
+    if (int rc = check_n(ctx, n)) return rc;
+    if (n_act < 0 || n_act > ctx->n_max) return fail_arg(ctx, "n_act out of range");
+    if (!active && n_act > n) return fail_arg(ctx, "n_act > n without an active list");
+    if (precision != H6_FP64 && precision != H6_MIXED) return fail_arg(ctx, "bad precision");
+    if (n_act == 0) return H6_OK;
+    H6_TRY(ctx,
+           launch_eval(ctx, 2, precision, src_from_pred(src, m), (int)n, active, (int)n_act,
+                       out_from_force(out), nullptr),
+           "evaluate");
+    return H6_OK;
+}
+
+int h6_correct(h6_ctx ctx, h6_state *st, const int32_t *active, int64_t n_act, const h6_force *f,
+               int64_t t_next, const h6_params *prm) {
+    if (!ctx) return H6_EINVAL;
+    if (!state_ok(st, true) || !active || !force_ok(f)) return fail_arg(ctx, "null array");
+    if (!params_ok(prm)) return fail_arg(ctx, "bad step parameters");
+    if (n_act < 0 || n_act > ctx->n_max) return fail_arg(ctx, "n_act out of range");
+    if (t_next <= 0) return fail_arg(ctx, "t_next must be positive");
+    H6_TRY(ctx, launch_correct(ctx, st, active, (int)n_act, f, t_next, 0.0, prm, false), "correct");
+    return H6_OK;
+}
+
+int h6_correct_shared(h6_ctx ctx, h6_state *st, int64_t n, const h6_force *f, double dt) {
+    if (!ctx) return H6_EINVAL;
+    if (!state_ok(st, false) || !force_ok(f)) return fail_arg(ctx, "null array");
+    if (int rc = check_n(ctx, n)) return rc;
+    if (!std::isfinite(dt) || dt <= 0.0) return fail_arg(ctx, "dt must be positive");
+    H6_TRY(ctx, launch_correct(ctx, st, nullptr, (int)n, f, 0, dt, nullptr, true), "correct");
+    return H6_OK;
+}
+
+int h6_init_forces(h6_ctx ctx, h6_state *st, int64_t n) {
+    if (!ctx) return H6_EINVAL;
+    if (!state_ok(st, false)) return fail_arg(ctx, "null array");
+    if (int rc = check_n(ctx, n)) return rc;
+    // pass 1: a, j from x, v
+    SrcPtrs s1;
+    for (int c = 0; c < 3; ++c) {
+        s1.x[c] = st->x[c];
+        s1.v[c] = st->v[c];
+        s1.a[c] = nullptr;
+        s1.j[c] = nullptr;
+    }
+    s1.m = st->m;
+    OutPtrs o1;
+    for (int c = 0; c < 12; ++c) o1.p[c] = nullptr;
+    for (int c = 0; c < 3; ++c) {
+        o1.p[c] = st->a[c];
+        o1.p[3 + c] = st->j[c];
+    }
+    H6_TRY(ctx, launch_eval(ctx, 1, H6_FP64, s1, (int)n, nullptr, (int)n, o1, nullptr), "init pass 1");
+    // pass 2: s, c with the pass-1 a and j as source acceleration and jerk
+    SrcPtrs s2 = s1;
+    for (int c = 0; c < 3; ++c) {
+        s2.a[c] = st->a[c];
+        s2.j[c] = st->j[c];
+    }
+    OutPtrs o2;
+    for (int c = 0; c < 12; ++c) o2.p[c] = nullptr;
+    for (int c = 0; c < 3; ++c) {
+        o2.p[6 + c] = st->s[c];
+        o2.p[9 + c] = st->c[c];
+    }
+    H6_TRY(ctx, launch_eval(ctx, 3, H6_FP64, s2, (int)n, nullptr, (int)n, o2, nullptr), "init pass 2");
+    return H6_OK;
+}
+
+int h6_initial_steps(h6_ctx ctx, h6_state *st, int64_t n, double eta_s, int lev_min, int lev_max) {
+    if (!ctx) return H6_EINVAL;
+    if (!state_ok(st, true)) return fail_arg(ctx, "null array");
+    if (int rc = check_n(ctx, n)) return rc;
+    if (!std::isfinite(eta_s) || eta_s <= 0.0 || lev_min < 0 || lev_max < lev_min ||
+        lev_max > kTickBits)
+        return fail_arg(ctx, "bad start-up step parameters");
+    H6_TRY(ctx, launch_initial_steps(ctx, st, (int)n, eta_s, lev_min, lev_max), "initial steps");
+    return H6_OK;
+}
+
+int h6_next_block(h6_ctx ctx, const h6_state *st, int64_t n, int32_t *active, int64_t *t_next,
+                  int64_t *n_act) {
+    if (!ctx) return H6_EINVAL;
+    if (!st || !st->t || !st->dt || !active || !t_next || !n_act) return fail_arg(ctx, "null pointer");
+    if (int rc = check_n(ctx, n)) return rc;
+    H6_TRY(ctx, launch_next_block(ctx, st, (int)n, active), "next block");
+    int64_t *h64 = (int64_t *)ctx->host;
+    int32_t *h32 = (int32_t *)((char *)ctx->host + 64);
+    H6_TRY(ctx,
+           hipMemcpyAsync(h64, ctx->sched64 + 1, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream),
+           "t_next readback");
+    H6_TRY(ctx, hipMemcpyAsync(h32, ctx->sched32, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream),
+           "n_act readback");
+    H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    *t_next = h64[0];
+    *n_act = h32[0];
+    return H6_OK;
+}
+
+int h6_block_step(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred, const h6_force *f,
+                  int32_t *active, const h6_params *prm, int64_t *t_next, int64_t *n_act) {
+    if (!ctx) return H6_EINVAL;
+    if (!state_ok(st, true) || !pred_ok(pred) || !force_ok(f) || !active || !t_next || !n_act)
+        return fail_arg(ctx, "null pointer");
+    if (!params_ok(prm)) return fail_arg(ctx, "bad step parameters");
+    if (int rc = check_n(ctx, n)) return rc;
+    int rc = h6_next_block(ctx, st, n, active, t_next, n_act);
+    if (rc) return rc;
+    if (*n_act < 1) return fail_arg(ctx, "empty block");
+    H6_TRY(ctx, launch_predict(ctx, st, (int)n, *t_next, 0.0, false, pred), "predict");
+    H6_TRY(ctx,
+           launch_eval(ctx, 2, prm->precision, src_from_pred(pred, st->m), (int)n, active,
+                       (int)*n_act, out_from_force(f), nullptr),
+           "evaluate");
+    H6_TRY(ctx, launch_correct(ctx, st, active, (int)*n_act, f, *t_next, 0.0, prm, false), "correct");
+    return H6_OK;
+}
+
+int h6_run_blocks(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred, const h6_force *f,
+                  int32_t *active, const h6_params *prm, int64_t t_end, h6_run_stats *stats) {
+    if (!ctx) return H6_EINVAL;
+    if (!state_ok(st, true) || !pred_ok(pred) || !force_ok(f) || !active)
+        return fail_arg(ctx, "null pointer");
+    if (!params_ok(prm)) return fail_arg(ctx, "bad step parameters");
+    if (int rc = check_n(ctx, n)) return rc;
+    h6_run_stats s = {0, 0, 0.0, 0};
+    for (;;) {
+        // next_block reports the smallest due time; stop once it passes t_end
+        int64_t tn = 0, na = 0;
+        int rc = h6_next_block(ctx, st, n, active, &tn, &na);
+        if (rc) return rc;
+        if (tn > t_end) {
+            s.t_end = t_end;
+            break;
+        }
+        H6_TRY(ctx, launch_predict(ctx, st, (int)n, tn, 0.0, false, pred), "predict");
+        H6_TRY(ctx,
+               launch_eval(ctx, 2, prm->precision, src_from_pred(pred, st->m), (int)n, active,
+                           (int)na, out_from_force(f), nullptr),
+               "evaluate");
+        H6_TRY(ctx, launch_correct(ctx, st, active, (int)na, f, tn, 0.0, prm, false), "correct");
+        s.blocks += 1;
+        s.particle_steps += na;
+        s.interactions += (double)na * (double)n;
+        s.t_end = tn;
+    }
+    if (stats) *stats = s;
+    return read_flags(ctx);
+}
+
+int h6_shared_steps(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred, const h6_force *f,
+                    double dt, int64_t nsteps, int precision) {
+    if (!ctx) return H6_EINVAL;
+    if (!state_ok(st, false) || !pred_ok(pred) || !force_ok(f)) return fail_arg(ctx, "null pointer");
+    if (int rc = check_n(ctx, n)) return rc;
+    if (!std::isfinite(dt) || dt <= 0.0 || nsteps < 0) return fail_arg(ctx, "bad dt or step count");
+    if (precision != H6_FP64 && precision != H6_MIXED) return fail_arg(ctx, "bad precision");
+    for (int64_t k = 0; k < nsteps; ++k) {
+        H6_TRY(ctx, launch_predict(ctx, st, (int)n, 0, dt, true, pred), "predict");
+        H6_TRY(ctx,
+               launch_eval(ctx, 2, precision, src_from_pred(pred, st->m), (int)n, nullptr, (int)n,
+                           out_from_force(f), nullptr),
+               "evaluate");
+        H6_TRY(ctx, launch_correct(ctx, st, nullptr, (int)n, f, 0, dt, nullptr, true), "correct");
+    }
+    return H6_OK;
+}
+
+int h6_energy(h6_ctx ctx, const h6_state *st, int64_t n, double out[5]) {
+    if (!ctx) return H6_EINVAL;
+    if (!state_ok(st, false) || !out) return fail_arg(ctx, "null pointer");
+    if (int rc = check_n(ctx, n)) return rc;
+    H6_TRY(ctx, launch_energy(ctx, st, (int)n), "energy");
+    double *h = (double *)((char *)ctx->host + 128);
+    H6_TRY(ctx, hipMemcpyAsync(h, ctx->ered, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+           "energy readback");
+    H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    std::memcpy(out, h, 5 * sizeof(double));
+    return H6_OK;
+}
+
+int h6_check_status(h6_ctx ctx) {
+    if (!ctx) return H6_EINVAL;
+    return read_flags(ctx);
+}
+
+}  // extern "C"

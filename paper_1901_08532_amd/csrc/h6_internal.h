@@ -1,0 +1,82 @@
+// Internal declarations of libh6 (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "h6.h"
+
+namespace h6 {
+
+// Particle ranges are addressed with 32-bit indices inside kernels.
+constexpr int64_t kMaxParticles = (int64_t)1 << 30;
+constexpr int kTickBits = H6_TICK_BITS;
+
+// Device status flags (bit set in ctx->flags[0]).
+constexpr int kFlagDtMin = 1;
+constexpr int kFlagNonFinite = 2;
+
+// Source (j-side) arrays of an evaluation, structure of arrays.
+struct SrcPtrs {
+    const double *x[3], *v[3], *a[3], *j[3];
+    const double *m;
+};
+
+// Output arrays by component: component c of target k of slice s lives at
+// p[c][s * slice_stride + k].
+struct OutPtrs {
+    double *p[12];
+};
+
+struct EvalConfig {
+    int block;   // threads per workgroup
+    int ipl;     // targets per thread
+    int n_split; // source slices
+};
+
+}  // namespace h6
+
+struct h6_ctx_s {
+    int64_t n_max = 0;
+    double eps = 0.0, eps2 = 0.0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int cfg_block = 0, cfg_ipl = 0, cfg_split = 0;  // 0: automatic
+    // scratch (device)
+    double *partial = nullptr;     // [n_split][ncomp][ld] partial sums
+    int64_t partial_cap = 0;       // doubles
+    int64_t *sched64 = nullptr;    // block minima, t_next
+    int32_t *sched32 = nullptr;    // block counts, offsets, n_act
+    unsigned *counters = nullptr;  // last-workgroup counters
+    int32_t *flags = nullptr;      // status bits
+    double *ered = nullptr;        // energy partials
+    int64_t sched_blocks = 0;      // capacity of the scheduler arrays
+    // pinned host staging for scheduler/energy readback
+    void *host = nullptr;
+    std::string last_error;
+};
+
+namespace h6 {
+
+// Launchers: enqueue on ctx->stream, return hipError_t.
+hipError_t launch_eval(h6_ctx ctx, int order, int precision, const SrcPtrs &src, int n,
+                       const int32_t *active, int n_act, const OutPtrs &out,
+                       EvalConfig *used);
+EvalConfig choose_eval_config(h6_ctx ctx, int order, int precision, int n, int n_act);
+
+hipError_t launch_predict(h6_ctx ctx, const h6_state *st, int n, int64_t t_tick, double dt,
+                          bool shared, const h6_pred *out);
+hipError_t launch_correct(h6_ctx ctx, h6_state *st, const int32_t *active, int n_act,
+                          const h6_force *f, int64_t t_next, double dt, const h6_params *prm,
+                          bool shared);
+hipError_t launch_initial_steps(h6_ctx ctx, h6_state *st, int n, double eta_s, int lev_min,
+                                int lev_max);
+hipError_t launch_next_block(h6_ctx ctx, const h6_state *st, int n, int32_t *active);
+hipError_t launch_energy(h6_ctx ctx, const h6_state *st, int n);
+
+int sched_blocks_for(int64_t n);
+int energy_blocks_for(int64_t n);
+
+}  // namespace h6

@@ -1,0 +1,473 @@
+// Integrator steps around the evaluation: predictor, corrector with
+// interpolation and time-step assignment, start-up steps, the block
+// scheduler, and the energy / angular momentum diagnostic.
+//
+// All of these are bandwidth- or latency-bound elementwise passes over
+// structure-of-arrays FP64 data: one particle per lane, coalesced loads
+// and stores, no LDS except for block-level reductions.
+#include "h6_internal.h"
+
+namespace h6 {
+namespace {
+
+constexpr double kTick = 1.0 / (double)((int64_t)1 << kTickBits);  // 2^-40
+
+__device__ __forceinline__ int ceil_div_dev(int a, int b) { return (a + b - 1) / b; }
+
+// Smallest level L >= lev_min with 2^(-k L) <= q, for q = (dt_crit)^k:
+// with q = f 2^e, f in [0.5, 1), the condition is -k L <= e - 1, so
+// L = ceil((1 - e) / k). q == 0 gives lev_cap (no admissible step);
+// q NaN or +inf gives lev_min.
+__device__ __forceinline__ int level_from_power(double q, int k, int lev_min, int lev_cap) {
+    if (!(q == q) || q == __builtin_inf()) return lev_min;
+    if (q <= 0.0) return lev_cap;
+    int e;
+    frexp(q, &e);
+    const int p = 1 - e;  // L = ceil(p / k)
+    int L = p >= 0 ? (p + k - 1) / k : -((-p) / k);
+    if (L < lev_min) L = lev_min;
+    if (L > lev_cap) L = lev_cap;
+    return L;
+}
+
+__device__ __forceinline__ int level_of_ticks(int64_t dt) {
+    return kTickBits - (63 - __builtin_clzll((unsigned long long)dt));
+}
+
+__device__ __forceinline__ double norm3(double a, double b, double c) {
+    return sqrt(fma(a, a, fma(b, b, c * c)));
+}
+
+// ---------------------------------------------------------------- predictor
+// Taylor prediction: x to 5th order, v to 4th, a to 3rd, Horner form.
+__global__ __launch_bounds__(256) void k_predict(h6_state st, int n, int64_t t_tick, double dt,
+                                                 int shared, h6_pred out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double d = shared ? dt : (double)(t_tick - st.t[i]) * kTick;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double x = st.x[c][i], v = st.v[c][i], a = st.a[c][i];
+        const double j = st.j[c][i], s = st.s[c][i], cr = st.c[c][i];
+        // a_p = a + d (j + d/2 (s + d/3 c))
+        const double ap = fma(d, fma(d * 0.5, fma(d * (1.0 / 3.0), cr, s), j), a);
+        // v_p = v + d (a + d/2 (j + d/3 (s + d/4 c)))
+        const double vp =
+            fma(d, fma(d * 0.5, fma(d * (1.0 / 3.0), fma(d * 0.25, cr, s), j), a), v);
+        // x_p = x + d (v + d/2 (a + d/3 (j + d/4 (s + d/5 c))))
+        const double xp = fma(
+            d, fma(d * 0.5, fma(d * (1.0 / 3.0), fma(d * 0.25, fma(d * 0.2, cr, s), j), a), v), x);
+        out.x[c][i] = xp;
+        out.v[c][i] = vp;
+        out.a[c][i] = ap;
+    }
+}
+
+// ---------------------------------------------------------------- corrector
+// 6th-order Hermite corrector, quintic interpolation of crackle, pop and
+// the fifth derivative at the step end, and the power-of-two step rule.
+template <bool SHARED>
+__global__ __launch_bounds__(256) void k_correct(h6_state st, const int32_t *__restrict__ active,
+                                                 int n_act, h6_force f, int64_t t_next, double dt_sh,
+                                                 double eta6, int lev_min, int lev_max,
+                                                 int32_t *flags) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_act) return;
+    const int i = SHARED ? k : active[k];
+    const int64_t dt_old = SHARED ? 0 : st.dt[i];
+    const double h = SHARED ? dt_sh : (double)dt_old * kTick;
+    const double h2 = h * h;
+    const double hinv = 1.0 / h;
+    const double hinv2 = hinv * hinv, hinv3 = hinv2 * hinv;
+    double a1n[3], j1n[3], s1n[3], cn[3], pn[3], dn[3];
+    bool finite = true;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double x0 = st.x[c][i], v0 = st.v[c][i];
+        const double a0 = st.a[c][i], j0 = st.j[c][i], s0 = st.s[c][i];
+        const double a1 = f.a[c][k], j1 = f.j[c][k], s1 = f.s[c][k];
+        // v1 = v0 + h/2 (a0 + a1) - h^2/10 (j1 - j0) + h^3/120 (s0 + s1)
+        const double v1 =
+            v0 + h * fma(h, fma(h * (1.0 / 120.0), s0 + s1, -0.1 * (j1 - j0)), 0.5 * (a0 + a1));
+        // x1 = x0 + h/2 (v0 + v1) - h^2/10 (a1 - a0) + h^3/120 (j0 + j1)
+        const double x1 =
+            x0 + h * fma(h, fma(h * (1.0 / 120.0), j0 + j1, -0.1 * (a1 - a0)), 0.5 * (v0 + v1));
+        const double da = a1 - a0;
+        // derivatives of the quintic through (a, j, s) at both ends, at the end
+        const double c1 = fma(h2, 9.0 * s1 - 3.0 * s0, fma(-h, fma(24.0, j0, 36.0 * j1), 60.0 * da)) * hinv3;
+        st.x[c][i] = x1;
+        st.v[c][i] = v1;
+        st.a[c][i] = a1;
+        st.j[c][i] = j1;
+        st.s[c][i] = s1;
+        st.c[c][i] = c1;
+        finite = finite && isfinite(x1) && isfinite(v1) && isfinite(c1);
+        if (!SHARED) {
+            const double p1 =
+                fma(h2, 36.0 * s1 - 24.0 * s0, fma(-h, fma(168.0, j0, 192.0 * j1), 360.0 * da)) *
+                (hinv3 * hinv);
+            const double d5 =
+                fma(60.0 * h2, s1 - s0, fma(-360.0 * h, j0 + j1, 720.0 * da)) * (hinv3 * hinv2);
+            a1n[c] = a1;
+            j1n[c] = j1;
+            s1n[c] = s1;
+            cn[c] = c1;
+            pn[c] = p1;
+            dn[c] = d5;
+        }
+    }
+    if (!finite) atomicOr(flags, kFlagNonFinite);
+    if (SHARED) return;
+    // generalized Aarseth criterion, order 6: dt^6 = eta^6 A1 / A4
+    const double A1 = fma(norm3(a1n[0], a1n[1], a1n[2]), norm3(s1n[0], s1n[1], s1n[2]),
+                          fma(j1n[0], j1n[0], fma(j1n[1], j1n[1], j1n[2] * j1n[2])));
+    const double A4 = fma(norm3(cn[0], cn[1], cn[2]), norm3(dn[0], dn[1], dn[2]),
+                          fma(pn[0], pn[0], fma(pn[1], pn[1], pn[2] * pn[2])));
+    const double q = (A1 / A4) * eta6;
+    const int lev_crit = level_from_power(q, 6, lev_min, lev_max + 1);
+    const int lev_old = level_of_ticks(dt_old);
+    int lev_new = lev_old;
+    if (lev_crit > lev_old) {
+        lev_new = lev_crit;
+    } else if (lev_crit < lev_old) {
+        const int64_t two_old = dt_old << 1;
+        if (t_next % two_old == 0) lev_new = lev_old - 1;
+    }
+    if (lev_new > lev_max) {
+        atomicOr(flags, kFlagDtMin);
+        lev_new = lev_max;
+    }
+    st.t[i] = t_next;
+    st.dt[i] = (int64_t)1 << (kTickBits - lev_new);
+}
+
+// ---------------------------------------------------------------- start-up steps
+// dt^2 = eta_s^2 (|a||s| + |j|^2) / (|j||c| + |s|^2)  (4th-order criterion)
+__global__ __launch_bounds__(256) void k_initial_steps(h6_state st, int n, double eta2, int lev_min,
+                                                       int lev_max, int32_t *flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double a0 = st.a[0][i], a1 = st.a[1][i], a2 = st.a[2][i];
+    const double j0 = st.j[0][i], j1 = st.j[1][i], j2 = st.j[2][i];
+    const double s0 = st.s[0][i], s1 = st.s[1][i], s2 = st.s[2][i];
+    const double c0 = st.c[0][i], c1 = st.c[1][i], c2 = st.c[2][i];
+    const double num = fma(norm3(a0, a1, a2), norm3(s0, s1, s2), fma(j0, j0, fma(j1, j1, j2 * j2)));
+    const double den = fma(norm3(j0, j1, j2), norm3(c0, c1, c2), fma(s0, s0, fma(s1, s1, s2 * s2)));
+    int L = level_from_power((num / den) * eta2, 2, lev_min, lev_max + 1);
+    if (L > lev_max) {
+        atomicOr(flags, kFlagDtMin);
+        L = lev_max;
+    }
+    st.t[i] = 0;
+    st.dt[i] = (int64_t)1 << (kTickBits - L);
+}
+
+// ---------------------------------------------------------------- scheduler
+// Three passes over fixed chunks of kSchedChunk particles per workgroup:
+//   1. chunk minima of t + dt; the last workgroup to finish reduces them to
+//      t_next;
+//   2. chunk counts of particles due at t_next; the last workgroup scans
+//      them into chunk offsets and the total n_act;
+//   3. each chunk writes its due particles, in index order, at its offset.
+constexpr int kSchedThreads = 256;
+constexpr int kSchedChunk = kSchedThreads * 16;
+
+// Ordered hand-off between workgroups of one launch: every workgroup
+// publishes its result, then increments the counter with a device-scope
+// release; the one that sees count == nblocks - 1 is the last, acquires,
+// and may read all published results. It resets the counter for the next
+// launch.
+__device__ __forceinline__ bool last_workgroup(unsigned *counter, unsigned nblocks) {
+    __shared__ bool is_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev =
+            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        is_last = (prev == nblocks - 1);
+        if (is_last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (is_last) __threadfence();
+    return is_last;
+}
+
+template <typename T>
+__device__ __forceinline__ T load_agent(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int64_t wave_min_i64(int64_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int64_t o = __shfl_xor(v, off, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int64_t block_min_i64(int64_t v) {
+    __shared__ int64_t wmin[kSchedThreads / 64];
+    v = wave_min_i64(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) wmin[w] = v;
+    __syncthreads();
+    int64_t r = wmin[0];
+#pragma unroll
+    for (int q = 1; q < kSchedThreads / 64; ++q) r = wmin[q] < r ? wmin[q] : r;
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kSchedThreads) void k_sched_min(const int64_t *__restrict__ t,
+                                                             const int64_t *__restrict__ dt, int n,
+                                                             int64_t *blockmin, unsigned *counter,
+                                                             int64_t *t_next) {
+    const int base = blockIdx.x * kSchedChunk;
+    const int end = min(n, base + kSchedChunk);
+    int64_t v = INT64_MAX;
+    for (int i = base + threadIdx.x; i < end; i += kSchedThreads) {
+        const int64_t due = t[i] + dt[i];
+        v = due < v ? due : v;
+    }
+    v = block_min_i64(v);
+    if (threadIdx.x == 0) blockmin[blockIdx.x] = v;
+    if (!last_workgroup(counter, gridDim.x)) return;
+    int64_t r = INT64_MAX;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kSchedThreads) {
+        const int64_t x = load_agent(&blockmin[b]);
+        r = x < r ? x : r;
+    }
+    r = block_min_i64(r);
+    if (threadIdx.x == 0) *t_next = r;
+}
+
+__global__ __launch_bounds__(kSchedThreads) void k_sched_count(const int64_t *__restrict__ t,
+                                                               const int64_t *__restrict__ dt,
+                                                               int n, const int64_t *t_next,
+                                                               int32_t *blockcnt, int32_t *blockoff,
+                                                               unsigned *counter, int32_t *n_act,
+                                                               int64_t *t_next_host_copy) {
+    const int64_t tn = *t_next;
+    const int base = blockIdx.x * kSchedChunk;
+    const int end = min(n, base + kSchedChunk);
+    int cnt = 0;
+    for (int i = base + threadIdx.x; i < end; i += kSchedThreads) cnt += (t[i] + dt[i] == tn);
+    // block sum
+    __shared__ int wsum[kSchedThreads / 64];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+#pragma unroll
+        for (int q = 0; q < kSchedThreads / 64; ++q) s += wsum[q];
+        blockcnt[blockIdx.x] = s;
+    }
+    if (!last_workgroup(counter, gridDim.x)) return;
+    if (threadIdx.x == 0) {
+        // exclusive scan over the (few hundred at most) chunk counts
+        int run = 0;
+        for (int b = 0; b < (int)gridDim.x; ++b) {
+            const int c = load_agent(&blockcnt[b]);
+            blockoff[b] = run;
+            run += c;
+        }
+        *n_act = run;
+        *t_next_host_copy = tn;
+    }
+}
+
+__global__ __launch_bounds__(kSchedThreads) void k_sched_compact(const int64_t *__restrict__ t,
+                                                                 const int64_t *__restrict__ dt,
+                                                                 int n, const int64_t *t_next,
+                                                                 const int32_t *blockoff,
+                                                                 int32_t *active) {
+    __shared__ int wcnt[kSchedThreads / 64];
+    const int64_t tn = *t_next;
+    const int base = blockIdx.x * kSchedChunk;
+    const int end = min(n, base + kSchedChunk);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int run = blockoff[blockIdx.x];
+    for (int r = base; r < end; r += kSchedThreads) {
+        const int i = r + threadIdx.x;
+        const bool due = i < end && (t[i] + dt[i] == tn);
+        const unsigned long long mask = __ballot(due);
+        const int before = __popcll(mask & ((1ull << lane) - 1ull));
+        if (lane == 0) wcnt[w] = __popcll(mask);
+        __syncthreads();
+        int woff = 0, tot = 0;
+#pragma unroll
+        for (int q = 0; q < kSchedThreads / 64; ++q) {
+            woff += q < w ? wcnt[q] : 0;
+            tot += wcnt[q];
+        }
+        if (due) active[run + woff + before] = i;
+        run += tot;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- energy
+constexpr int kEnergyThreads = 256;
+
+__device__ __forceinline__ double rsqrt_f64(double r2) {
+    double y = __builtin_amdgcn_rsq(r2);
+    double t = r2 * y;
+    double e = fma(-t, y, 1.0);
+    double p = fma(e, 0.375, 0.5);
+    double ye = y * e;
+    return fma(ye, p, y);
+}
+
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    const double bp = s - a;
+    e = (a - (s - bp)) + (b - bp);
+}
+
+// Per particle: potential -m_i/2 sum_{j != i} m_j / sqrt(r^2+eps^2)
+// (compensated over source tiles), kinetic m v^2/2, angular momentum
+// m x cross v; workgroup sums as compensated (hi, lo) trees; the last
+// workgroup adds the workgroup sums in order.
+__global__ __launch_bounds__(kEnergyThreads) void k_energy(h6_state st, int n, double eps2,
+                                                           double *partial, unsigned *counter,
+                                                           double *out) {
+    __shared__ double4 tile[kEnergyThreads];  // x, y, z, m
+    __shared__ double red_hi[5][kEnergyThreads];
+    __shared__ double red_lo[5][kEnergyThreads];
+    const int tid = threadIdx.x;
+    const int i = blockIdx.x * kEnergyThreads + tid;
+    const int ic = i < n ? i : n - 1;
+    const double xi0 = st.x[0][ic], xi1 = st.x[1][ic], xi2 = st.x[2][ic];
+    double phi_hi = 0.0, phi_lo = 0.0;
+    for (int jt = 0; jt < n; jt += kEnergyThreads) {
+        __syncthreads();
+        const int jj = jt + tid;
+        tile[tid] = jj < n ? make_double4(st.x[0][jj], st.x[1][jj], st.x[2][jj], st.m[jj])
+                           : make_double4(1.0e18, 1.0e18, 1.0e18, 0.0);
+        __syncthreads();
+        double acc = 0.0;
+        for (int q = 0; q < kEnergyThreads; ++q) {
+            const double4 r = tile[q];
+            const double dx = r.x - xi0, dy = r.y - xi1, dz = r.z - xi2;
+            double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
+            const bool self = (jt + q) == ic;
+            r2 = self ? 1.0 : r2;
+            const double mj = self ? 0.0 : r.w;
+            acc = fma(mj, rsqrt_f64(r2), acc);
+        }
+        double s, e;
+        two_sum(phi_hi, acc, s, e);
+        phi_hi = s;
+        phi_lo += e;
+    }
+    double v[5] = {0, 0, 0, 0, 0};
+    if (i < n) {
+        const double m = st.m[i];
+        const double vx = st.v[0][i], vy = st.v[1][i], vz = st.v[2][i];
+        v[0] = 0.5 * m * fma(vx, vx, fma(vy, vy, vz * vz));
+        v[1] = -0.5 * m * (phi_hi + phi_lo);
+        v[2] = m * (xi1 * vz - xi2 * vy);
+        v[3] = m * (xi2 * vx - xi0 * vz);
+        v[4] = m * (xi0 * vy - xi1 * vx);
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        red_hi[q][tid] = v[q];
+        red_lo[q][tid] = 0.0;
+    }
+    __syncthreads();
+    for (int w = kEnergyThreads / 2; w >= 1; w >>= 1) {
+        if (tid < w) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                double s, e;
+                two_sum(red_hi[q][tid], red_hi[q][tid + w], s, e);
+                red_hi[q][tid] = s;
+                red_lo[q][tid] += red_lo[q][tid + w] + e;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid < 5) {
+        partial[2 * (blockIdx.x * 5 + tid)] = red_hi[tid][0];
+        partial[2 * (blockIdx.x * 5 + tid) + 1] = red_lo[tid][0];
+    }
+    if (!last_workgroup(counter, gridDim.x)) return;
+    if (tid < 5) {
+        double hi = 0.0, lo = 0.0;
+        for (int b = 0; b < (int)gridDim.x; ++b) {
+            double s, e;
+            two_sum(hi, load_agent(&partial[2 * (b * 5 + tid)]), s, e);
+            hi = s;
+            lo += e + load_agent(&partial[2 * (b * 5 + tid) + 1]);
+        }
+        out[tid] = hi + lo;
+    }
+}
+
+}  // namespace
+
+int sched_blocks_for(int64_t n) { return (int)((n + kSchedChunk - 1) / kSchedChunk); }
+int energy_blocks_for(int64_t n) { return (int)((n + kEnergyThreads - 1) / kEnergyThreads); }
+
+hipError_t launch_predict(h6_ctx ctx, const h6_state *st, int n, int64_t t_tick, double dt,
+                          bool shared, const h6_pred *out) {
+    hipLaunchKernelGGL(k_predict, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, *st, n, t_tick,
+                       dt, shared ? 1 : 0, *out);
+    return hipGetLastError();
+}
+
+hipError_t launch_correct(h6_ctx ctx, h6_state *st, const int32_t *active, int n_act,
+                          const h6_force *f, int64_t t_next, double dt, const h6_params *prm,
+                          bool shared) {
+    if (n_act <= 0) return hipSuccess;
+    dim3 grid((n_act + 255) / 256);
+    if (shared) {
+        hipLaunchKernelGGL(k_correct<true>, grid, dim3(256), 0, ctx->stream, *st, active, n_act, *f,
+                           (int64_t)0, dt, 0.0, 0, 0, ctx->flags);
+    } else {
+        const double e = prm->eta, e2 = e * e;
+        hipLaunchKernelGGL(k_correct<false>, grid, dim3(256), 0, ctx->stream, *st, active, n_act,
+                           *f, t_next, 0.0, e2 * e2 * e2, prm->lev_min, prm->lev_max, ctx->flags);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_initial_steps(h6_ctx ctx, h6_state *st, int n, double eta_s, int lev_min,
+                                int lev_max) {
+    hipLaunchKernelGGL(k_initial_steps, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, *st, n,
+                       eta_s * eta_s, lev_min, lev_max, ctx->flags);
+    return hipGetLastError();
+}
+
+// Scratch layout (ctx->sched64): [0] t_next, [1] t_next copy for the host,
+// [2..] chunk minima. ctx->sched32: [0] n_act, [1..nb] counts,
+// [1+nb..2nb] offsets. counters[0..1]: min and count hand-offs.
+hipError_t launch_next_block(h6_ctx ctx, const h6_state *st, int n, int32_t *active) {
+    const int nb = sched_blocks_for(n);
+    int64_t *t_next = ctx->sched64;
+    int64_t *t_copy = ctx->sched64 + 1;
+    int64_t *bmin = ctx->sched64 + 2;
+    int32_t *n_act = ctx->sched32;
+    int32_t *bcnt = ctx->sched32 + 1;
+    int32_t *boff = ctx->sched32 + 1 + nb;
+    hipLaunchKernelGGL(k_sched_min, dim3(nb), dim3(kSchedThreads), 0, ctx->stream, st->t, st->dt, n,
+                       bmin, ctx->counters, t_next);
+    hipLaunchKernelGGL(k_sched_count, dim3(nb), dim3(kSchedThreads), 0, ctx->stream, st->t, st->dt,
+                       n, (const int64_t *)t_next, bcnt, boff, ctx->counters + 1, n_act, t_copy);
+    hipLaunchKernelGGL(k_sched_compact, dim3(nb), dim3(kSchedThreads), 0, ctx->stream, st->t,
+                       st->dt, n, (const int64_t *)t_next, (const int32_t *)boff, active);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy(h6_ctx ctx, const h6_state *st, int n) {
+    const int nb = energy_blocks_for(n);
+    hipLaunchKernelGGL(k_energy, dim3(nb), dim3(kEnergyThreads), 0, ctx->stream, *st, n, ctx->eps2,
+                       ctx->ered + 8, ctx->counters + 2, ctx->ered);
+    return hipGetLastError();
+}
+
+}  // namespace h6

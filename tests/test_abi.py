@@ -1,0 +1,60 @@
+"""The C ABI library loads and exports every function include/h6.h declares,
+and argument validation answers before any device work (CPU only)."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1901_08532_amd import h6
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "h6.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(h6_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_names():
+    assert _declared() == sorted(h6.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = C.CDLL(h6.LIB_PATH)
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_error_texts():
+    L = h6.lib()
+    for code in (h6.H6_OK, h6.H6_EINVAL, h6.H6_ENOMEM, h6.H6_EHIP, h6.H6_ESTATE, h6.H6_EDTMIN,
+                 h6.H6_ENONFINITE):
+        assert L.h6_strerror(code)
+    assert L.h6_strerror(12345) == b"unknown error"
+    assert L.h6_last_error(None) == b""
+
+
+def test_null_context_and_bad_create_arguments():
+    L = h6.lib()
+    assert L.h6_create(None, 10, 0.1, None) == h6.H6_EINVAL
+    out = C.c_void_p()
+    assert L.h6_create(C.byref(out), 0, 0.1, None) == h6.H6_EINVAL
+    assert L.h6_create(C.byref(out), 10, -1.0, None) == h6.H6_EINVAL
+    assert L.h6_create(C.byref(out), 10, float("nan"), None) == h6.H6_EINVAL
+    assert out.value is None
+    assert L.h6_destroy(None) == h6.H6_OK
+    st = h6.h6_state()
+    assert L.h6_evaluate(None, None, None, 1, None, 1, 0, None) == h6.H6_EINVAL
+    assert L.h6_energy(None, C.byref(st), 1, None) == h6.H6_EINVAL
+    assert L.h6_check_status(None) == h6.H6_EINVAL
+    assert L.h6_set_eval_config(None, 64, 1, 1) == h6.H6_EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(h6, "_lib", None)
+    monkeypatch.setattr(h6, "LIB_PATH", "/nonexistent/libh6.so")
+    with pytest.raises(h6.H6Error):
+        h6.lib()

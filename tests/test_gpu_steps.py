@@ -1,0 +1,313 @@
+"""GPU parity of the integrator steps against the FP64 oracle.
+
+Predictor, corrector/interpolation/step rule, start-up passes, initial
+steps, block scheduler (bit-exact), energy, a 100-step shared-step run
+(N = 1024, dt = 1/1024, eps = 1e-4) and block-step runs from one state.
+
+Floating-point results are compared against tolerances scaled by the size
+of the terms that enter them; integer results (block times, active lists,
+steps) bit-exactly, except that a step level decided by a criterion value
+within 1e-9 (relative) of a power of two may take either neighbour.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1901_08532_amd import h6, ics
+from _gpu import DEV, from_rows, to_rows, vec_rel_err
+
+pytestmark = pytest.mark.gpu
+
+TB = h6.TICK_BITS
+EPS = 1e-4
+
+
+def _state_tensor(d):
+    return to_rows(d["x"], d["v"], d["a"], d["j"], d["s"], d["c"])
+
+
+def _mt(m):
+    return torch.from_numpy(np.ascontiguousarray(m)).to(DEV)
+
+
+def test_predictor_matches_oracle():
+    n = 5000
+    d = ics.random_state(n, 1)
+    rng = np.random.Generator(np.random.PCG64(2))
+    lev = rng.integers(4, 20, n)
+    dt = (1 << (TB - lev)).astype(np.int64)
+    t_next = 7 << (TB - 4)
+    t = t_next - dt * rng.integers(1, 3, n)  # some predicted over two steps
+    S = _state_tensor(d)
+    T = torch.from_numpy(np.stack([t, dt])).to(DEV).contiguous()
+    P = torch.zeros((9, n), dtype=torch.float64, device=DEV)
+    ctx = h6.Context(n, EPS)
+    ctx.h6_predict(S, _mt(d["m"]), T, t_next, P)
+    torch.cuda.synchronize()
+    delta = (t_next - t) * 2.0 ** -TB
+    want = oracle.predict(d["x"], d["v"], d["a"], d["j"], d["s"], d["c"], delta)
+    # scale: sum of the absolute Taylor terms
+    D = delta[:, None]
+    scale = [np.abs(d["x"]) + np.abs(d["v"] * D) + np.abs(d["a"] * D ** 2) + np.abs(d["j"] * D ** 3)
+             + np.abs(d["s"] * D ** 4) + np.abs(d["c"] * D ** 5),
+             np.abs(d["v"]) + np.abs(d["a"] * D) + np.abs(d["j"] * D ** 2) + np.abs(d["s"] * D ** 3)
+             + np.abs(d["c"] * D ** 4),
+             np.abs(d["a"]) + np.abs(d["j"] * D) + np.abs(d["s"] * D ** 2) + np.abs(d["c"] * D ** 3)]
+    for k in range(3):
+        got = from_rows(P, k)
+        assert np.all(np.abs(got - want[k]) <= 8e-16 * scale[k])
+    # shared form: one interval for all
+    ctx.h6_predict_dt(S, _mt(d["m"]), 0.01, P)
+    torch.cuda.synchronize()
+    want = oracle.predict(d["x"], d["v"], d["a"], d["j"], d["s"], d["c"], 0.01)
+    for k in range(3):
+        assert np.allclose(from_rows(P, k), want[k], rtol=1e-14, atol=1e-15)
+
+
+def _smooth_case(n, seed, lev_lo=4, lev_hi=12):
+    """States with a(t) a random degree-7 polynomial on a per-particle time
+    scale, so the criterion sees realistic derivative ratios."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tau = 2.0 ** rng.uniform(-9, -1, n)[:, None]
+    coef = rng.normal(0, 1, (8, n, 3))
+    lev = rng.integers(lev_lo, lev_hi, n)
+    dt = (1 << (TB - lev)).astype(np.int64)
+    h = dt * 2.0 ** -TB
+
+    def deriv(t, k):  # k-th derivative of a at time t (t shape (n,1))
+        out = np.zeros((n, 3))
+        for p in range(k, 8):
+            out += coef[p] * (t / tau) ** (p - k) / math.factorial(p - k) / tau ** k
+        return out
+
+    z = np.zeros((n, 1))
+    H = h[:, None]
+    st = {"x": rng.normal(0, 1, (n, 3)), "v": rng.normal(0, 1, (n, 3)),
+          "a": deriv(z, 0), "j": deriv(z, 1), "s": deriv(z, 2), "c": deriv(z, 3),
+          "m": rng.uniform(0.5, 1.5, n) / n}
+    f = {"a": deriv(H, 0), "j": deriv(H, 1), "s": deriv(H, 2)}
+    return st, f, dt, h
+
+
+def _levels_agree(got_dt, want_lev, crit, lev_old_dt, t_next, lev_min, lev_max):
+    """got_dt ticks vs oracle levels; near-threshold criterion values may
+    round either way."""
+    got_lev = TB - np.log2(got_dt).astype(np.int64)
+    bad = np.nonzero(got_lev != want_lev)[0]
+    for i in bad:
+        frac = math.log2(crit[i]) if crit[i] > 0 else 0.0
+        near = abs(frac - round(frac)) < 1e-9
+        lev_old = TB - int(math.log2(lev_old_dt[i]))
+        alts = set()
+        for lc in (oracle.level_of(crit[i] * (1 + 1e-9), lev_min, lev_max + 1),
+                   oracle.level_of(crit[i] * (1 - 1e-9), lev_min, lev_max + 1)):
+            alts.add(min(oracle.next_level(lev_old, lc, t_next), lev_max))
+        assert near and got_lev[i] in alts, (i, got_lev[i], want_lev[i], crit[i])
+    return len(bad)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 3), (777, 4), (20000, 5)])
+def test_corrector_and_step_rule_match_oracle(n, seed):
+    st, f, dt, h = _smooth_case(n, seed)
+    eta, lev_min, lev_max = 0.4, 4, 40
+    t_next = 5 << (TB - 3)  # multiple of every step, commensurate for some growths
+    t = t_next - dt
+    rng = np.random.Generator(np.random.PCG64(seed + 100))
+    n_act = max(1, n // 2)
+    act = np.sort(rng.choice(n, n_act, replace=False)).astype(np.int32)
+    S = _state_tensor(st)
+    T = torch.from_numpy(np.stack([t, dt])).to(DEV).contiguous()
+    # forces are given in active order
+    F = to_rows(f["a"][act], f["j"][act], f["s"][act])
+    ctx = h6.Context(n, EPS)
+    ctx.h6_correct(S, _mt(st["m"]), T, torch.from_numpy(act).to(DEV), n_act, F, t_next, eta,
+                   lev_min, lev_max)
+    assert ctx.h6_check_status() == h6.H6_OK
+    x1, v1, c1, p1, d5 = oracle.correct(st["x"][act], st["v"][act], st["a"][act], st["j"][act],
+                                        st["s"][act], f["a"][act], f["j"][act], f["s"][act], h[act])
+    Sg = {k: from_rows(S, i) for i, k in enumerate(("x", "v", "a", "j", "s", "c"))}
+    H = h[act][:, None]
+    a0, j0, s0 = st["a"][act], st["j"][act], st["s"][act]
+    a1, j1, s1 = f["a"][act], f["j"][act], f["s"][act]
+    sx = np.abs(st["x"][act]) + H * (np.abs(st["v"][act]) + np.abs(v1)) + H ** 2 * (np.abs(a0) + np.abs(a1)) + H ** 3 * (np.abs(j0) + np.abs(j1))
+    sv = np.abs(st["v"][act]) + H * (np.abs(a0) + np.abs(a1)) + H ** 2 * (np.abs(j0) + np.abs(j1)) + H ** 3 * (np.abs(s0) + np.abs(s1))
+    sc = (60 * (np.abs(a0) + np.abs(a1)) + H * (24 * np.abs(j0) + 36 * np.abs(j1))
+          + H ** 2 * (9 * np.abs(s1) + 3 * np.abs(s0))) / H ** 3
+    assert np.all(np.abs(Sg["x"][act] - x1) <= 4e-16 * 8 * sx)
+    assert np.all(np.abs(Sg["v"][act] - v1) <= 4e-16 * 8 * sv)
+    assert np.all(np.abs(Sg["c"][act] - c1) <= 4e-16 * 16 * sc)
+    for k, ref in (("a", a1), ("j", j1), ("s", s1)):
+        assert np.array_equal(Sg[k][act], ref)
+    # untouched particles
+    rest = np.setdiff1d(np.arange(n), act)
+    for k in ("x", "v", "a", "j", "s", "c"):
+        assert np.array_equal(Sg[k][rest], st[k][rest])
+    Tg = T.cpu().numpy()
+    assert np.all(Tg[0][act] == t_next) and np.array_equal(Tg[0][rest], t[rest])
+    assert np.array_equal(Tg[1][rest], dt[rest])
+    crit = np.array([oracle.dt_crit6(a1[k], j1[k], s1[k], c1[k], p1[k], d5[k], eta)
+                     for k in range(n_act)])
+    want = np.array([min(oracle.next_level(TB - int(math.log2(dt[i])),
+                                           oracle.level_of(crit[k], lev_min, lev_max + 1), t_next),
+                         lev_max) for k, i in enumerate(act)])
+    nbad = _levels_agree(Tg[1][act], want, crit, dt[act], t_next, lev_min, lev_max)
+    assert nbad <= max(1, n_act // 1000)
+
+
+def test_shared_corrector_matches_oracle():
+    n = 3000
+    st, f, _, _ = _smooth_case(n, 9)
+    h = 1.0 / 512
+    # f evaluated at each particle's own h; reuse as generic inputs
+    S = _state_tensor(st)
+    F = to_rows(f["a"], f["j"], f["s"])
+    ctx = h6.Context(n, EPS)
+    ctx.h6_correct_shared(S, _mt(st["m"]), F, h)
+    assert ctx.h6_check_status() == h6.H6_OK
+    x1, v1, c1, _, _ = oracle.correct(st["x"], st["v"], st["a"], st["j"], st["s"], f["a"], f["j"],
+                                      f["s"], h)
+    assert np.allclose(from_rows(S, 0), x1, rtol=1e-13, atol=1e-14)
+    assert np.allclose(from_rows(S, 1), v1, rtol=1e-13, atol=1e-14)
+    sc = (60 * (np.abs(st["a"]) + np.abs(f["a"])) + h * (24 * np.abs(st["j"]) + 36 * np.abs(f["j"]))
+          + h ** 2 * (9 * np.abs(f["s"]) + 3 * np.abs(st["s"]))) / h ** 3
+    assert np.all(np.abs(from_rows(S, 5) - c1) <= 1e-14 * sc)
+
+
+@pytest.mark.parametrize("n", [1, 4095, 4096, 4097, 70000])
+def test_scheduler_is_exact(n):
+    rng = np.random.Generator(np.random.PCG64(n))
+    lev = rng.integers(4, 14, n)
+    dt = (1 << (TB - lev)).astype(np.int64)
+    t = (rng.integers(0, 16, n) * dt).astype(np.int64)
+    if n == 4096:
+        t[:] = 0
+        dt[:] = 1 << (TB - 6)  # everyone due together
+    T = torch.from_numpy(np.stack([t, dt])).to(DEV).contiguous()
+    S = torch.zeros((18, n), dtype=torch.float64, device=DEV)
+    act = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+    ctx = h6.Context(n, EPS)
+    for rep in range(2):  # counters reset between launches
+        tn, na = ctx.h6_next_block(S, _mt(np.ones(n)), T, act)
+        want_tn, want_act = oracle.next_block(t, dt)
+        assert tn == want_tn and na == len(want_act)
+        assert np.array_equal(act.cpu().numpy()[:na], want_act)
+
+
+@pytest.mark.parametrize("n", [1024, 3001])
+def test_startup_passes_match_oracle(n):
+    x, v, m = ics.plummer(n, 50 + n)
+    sysg = h6.System(x, v, m, EPS)
+    sysg.startup()
+    torch.cuda.synchronize()
+    want = oracle.startup(x, v, m, EPS ** 2)
+    for k, name in enumerate("ajsc"):
+        err = vec_rel_err(sysg.field(name), want[k])
+        tol = 1e-12 if name != "c" else 1e-11
+        assert err.max() <= tol, (name, err.max())
+
+
+def test_initial_steps_match_oracle():
+    n = 4096
+    x, v, m = ics.plummer(n, 60)
+    sysg = h6.System(x, v, m, EPS)
+    sysg.startup(eta_s=0.1, lev_min=4, lev_max=30)
+    assert sysg.ctx.h6_check_status() == h6.H6_OK
+    a, j, s, c = oracle.startup(x, v, m, EPS ** 2)
+    rc, dt_want = oracle.initial_levels(a, j, s, c, 0.1, 4, 30)
+    assert rc == 0
+    Tg = sysg.T.cpu().numpy()
+    assert np.all(Tg[0] == 0)
+    mism = np.nonzero(Tg[1] != dt_want)[0]
+    for i in mism:  # only near-threshold values may differ
+        d = oracle.dt_crit4(a[i], j[i], s[i], c[i], 0.1)
+        frac = math.log2(d)
+        assert abs(frac - round(frac)) < 1e-9
+    assert len(mism) <= 2
+
+
+def test_energy_matches_oracle():
+    n = 5000
+    x, v, m = ics.plummer(n, 70)
+    m = ics.salpeter_masses(n, 71)
+    sysg = h6.System(x, v, m, EPS)
+    ek, ep, L = sysg.energy()
+    wk, wp, wL = oracle.energy(x, v, m, EPS ** 2)
+    assert abs(ek - wk) <= 1e-13 * abs(wk)
+    assert abs(ep - wp) <= 1e-13 * abs(wp)
+    scaleL = np.abs(m[:, None] * np.cross(x, v)).sum()
+    assert np.abs(np.array(L) - wL).max() <= 1e-14 * scaleL
+    # a single particle has no potential energy
+    s1 = h6.System(x[:1], v[:1], m[:1], EPS)
+    assert s1.energy()[1] == 0.0
+
+
+def test_shared_run_c1_matches_oracle():
+    # N = 1024, eps = 1e-4, start-up plus 100 shared steps of 1/1024
+    n = 1024
+    x, v, m = ics.plummer(n, 1)
+    sysg = h6.System(x, v, m, EPS)
+    sysg.startup()
+    sysg.shared_steps(1.0 / 1024, 100)
+    torch.cuda.synchronize()
+    st = oracle.State(x, v, m, EPS ** 2)
+    st.startup()
+    st.shared_steps(1.0 / 1024, 100)
+    for name in ("x", "v"):
+        err = vec_rel_err(sysg.field(name), getattr(st, name))
+        assert err.max() < 1e-9, (name, err.max())
+    for name in ("a", "j", "s"):
+        err = vec_rel_err(sysg.field(name), getattr(st, name))
+        assert np.median(err) < 1e-9, (name, np.median(err))
+    e_g = sum(sysg.energy()[:2])
+    e_o = sum(st.energy()[:2])
+    assert abs(e_g - e_o) < 1e-10 * abs(e_o)
+
+
+def _synced_copy(st):
+    """Copy an oracle state into a GPU system (inputs flow oracle -> GPU only)."""
+    sysg = h6.System(st.x, st.v, st.m, math.sqrt(st.eps2))
+    for k, name in enumerate(("x", "v", "a", "j", "s", "c")):
+        sysg.S[3 * k:3 * k + 3] = torch.from_numpy(np.ascontiguousarray(getattr(st, name).T)).to(DEV)
+    sysg.T[0] = torch.from_numpy(st.t).to(DEV)
+    sysg.T[1] = torch.from_numpy(st.dt).to(DEV)
+    return sysg
+
+
+def test_block_steps_match_oracle():
+    n = 2048
+    x, v, m = ics.plummer(n, 80)
+    st = oracle.State(x, v, m, EPS ** 2)
+    assert st.startup(eta_s=0.1, lev_min=4, lev_max=30) == 0
+    sysg = _synced_copy(st)
+    for blk in range(40):
+        rc, tn, na = st.block_step(0.4, 4, 30)
+        assert rc == 0
+        tg, nag = sysg.block_step(0.4, 4, 30)
+        assert (tg, nag) == (tn, na), blk
+    torch.cuda.synchronize()
+    assert np.array_equal(sysg.T.cpu().numpy(), np.stack([st.t, st.dt]))
+    for name in ("x", "v", "a", "j", "s"):
+        err = vec_rel_err(sysg.field(name), getattr(st, name))
+        assert err.max() < 1e-9, (name, err.max())
+
+
+def test_run_blocks_reaches_sync_time():
+    n = 4096
+    x, v, m = ics.plummer(n, 90)
+    sysg = h6.System(x, v, m, EPS)
+    sysg.startup(eta_s=0.1, lev_min=4, lev_max=30)
+    e0 = sum(sysg.energy()[:2])
+    t_end = 2 << (TB - 4)  # 1/8 time unit
+    rc, stats = sysg.run_blocks(t_end, 0.4, 4, 30)
+    assert rc == h6.H6_OK
+    Tg = sysg.T.cpu().numpy()
+    assert np.all(Tg[0] == t_end)
+    assert np.all(Tg[0] % Tg[1] == 0) and np.all(Tg[1] <= 1 << (TB - 4))
+    assert stats.blocks > 1 and stats.particle_steps >= n
+    assert stats.interactions == pytest.approx(stats.particle_steps * n)
+    e1 = sum(sysg.energy()[:2])
+    assert abs(e1 - e0) / abs(e0) < 1e-7
