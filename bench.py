@@ -1,0 +1,256 @@
+"""Benchmark of the Hermite-6 block-step hot path on one MI355X.
+
+Workload: Plummer sphere, N = 65536 equal masses, Henon units, Plummer
+softening eps = 1e-4, FP64, block time steps (power-of-two steps from the
+6th-order generalized Aarseth criterion, eta = 0.4, largest step 1/16).
+
+One "step" is one pass of the whole hot path over one synchronisation
+interval: every block step (scheduler, predictor of all particles, a/j/s
+evaluation of the active ones, slice reduction, corrector with
+interpolation and step assignment) until all particles reach the next
+multiple of 1/16, then the energy / angular-momentum diagnostic at that
+sync time. The default 16 steps integrate one time unit. Warm-up steps run
+first from the start-up state, which is then restored, so the timed steps
+always integrate [0, K/16].
+
+value = sum over blocks of N_active * N (the self pair counted, as the
+kernel evaluates it branch-free) divided by the wall time of the K steps.
+roofline: the dominant evaluation-kernel instantiation, 78 flops per
+interaction divided by its HIP-event-measured duration, against the FP64
+vector peak.
+cpu_baseline: the FP64 CPU oracle, timed on a bounded sample of the same
+workload (its a/j/s evaluation of sampled targets against all sources).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "a/j/s pair interactions/s, % of vector FP peak, at stated rel. error vs FP64"
+FLOPS_PER_INTERACTION = 78  # FMA 2, rsqrt 1, potential excluded
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eval_f64_hbm_traffic.txt")
+EVAL_SOURCE = os.path.join(ROOT, "paper_1901_08532_amd", "csrc", "eval.hip")
+
+
+def _log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def _traffic_per_launch(block, ipl):
+    """HBM bytes per launch of the given instantiation from the committed
+    rocprofv3 counter summary, or None when the kernel source changed since
+    the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    want = hashlib.sha256(open(EVAL_SOURCE, "rb").read()).hexdigest()
+    fields = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("eval_source_sha256") != want:
+        return None
+    key = "hbm_bytes_per_launch_b%d_i%d" % (block, ipl)
+    return float(fields[key]) if key in fields else None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=16)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1901_08532_amd import h6, ics
+
+    torch.cuda.set_device(0)
+    n, eps, eta, lev_min, lev_max = args.n, 1e-4, 0.4, 4, 30
+    prec = h6.H6_FP64 if args.precision == "fp64" else h6.H6_MIXED
+    sync_ticks = 1 << (h6.TICK_BITS - lev_min)
+
+    _log("inputs: Plummer N=%d seed=%d" % (n, args.seed))
+    x, v, m = ics.plummer(n, args.seed)
+    sysg = h6.System(x, v, m, eps)
+    sysg.startup(eta_s=0.1, lev_min=lev_min, lev_max=lev_max)
+    rc = sysg.ctx.h6_check_status()
+    if rc != h6.H6_OK:
+        raise h6.H6Error(rc, "start-up")
+    S0, T0 = sysg.S.clone(), sysg.T.clone()
+    e_start = sysg.energy()
+    E0 = e_start[0] + e_start[1]
+
+    def one_step(k):
+        rc, stats = sysg.run_blocks((k + 1) * sync_ticks, eta, lev_min, lev_max, prec, check=False)
+        if rc != h6.H6_OK:
+            raise h6.H6Error(rc, "h6_run_blocks", h6.lib().h6_last_error(sysg.ctx.handle).decode())
+        e = sysg.energy()
+        return stats, e
+
+    for w in range(args.warmup):
+        st, _ = one_step(w)
+        _log("warmup step %d: %d blocks" % (w, st.blocks))
+    sysg.S.copy_(S0)
+    sysg.T.copy_(T0)
+    sysg.ctx.h6_profile_enable(True)
+    torch.cuda.synchronize()
+
+    blocks = psteps = 0
+    inter = 0.0
+    drift = 0.0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        st, e = one_step(k)
+        blocks += st.blocks
+        psteps += st.particle_steps
+        inter += st.interactions
+        drift = max(drift, abs(e[0] + e[1] - E0) / abs(E0))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = sysg.ctx.h6_profile_read()
+    sysg.ctx.h6_profile_enable(False)
+    wall = t1 - t0
+    value = inter / wall if wall > 0 else 0.0
+    _log("timed %d steps: %d blocks, %.3e interactions, %.3f s" % (args.steps, blocks, inter, wall))
+
+    # per instantiation (summed over active-set bins) and per active-set bin
+    evals = [p for p in prof if p["order"] == 2]
+    inst = {}
+    bins = {}
+    for p in evals:
+        key = (p["kind"], p["block"], p["ipl"])
+        d = inst.setdefault(key, {"kind": p["kind"], "block": p["block"], "ipl": p["ipl"],
+                                  "launches": 0, "interactions": 0.0, "kernel_ms": 0.0})
+        b = bins.setdefault(p["nact_log2"], {"launches": 0, "interactions": 0.0, "kernel_ms": 0.0})
+        for tgt in (d, b):
+            tgt["launches"] += p["launches"]
+            tgt["interactions"] += p["interactions"]
+            tgt["kernel_ms"] += p["kernel_ms"]
+    dom = max(inst.values(), key=lambda p: p["kernel_ms"])
+    eval_ms = sum(p["kernel_ms"] for p in evals)
+    by_active = []
+    for b in sorted(bins):
+        d = bins[b]
+        rate = d["interactions"] / (d["kernel_ms"] * 1e-3)
+        by_active.append({"n_act_from": 1 << b, "n_act_below": 1 << (b + 1), "launches": d["launches"],
+                          "interactions": d["interactions"], "eval_ms": d["kernel_ms"],
+                          "eval_interactions_per_s": rate,
+                          "eval_pct_fp64_peak": 100.0 * rate * FLOPS_PER_INTERACTION / (FP64_PEAK_TFLOPS * 1e12)})
+    achieved = FLOPS_PER_INTERACTION * dom["interactions"] / (dom["kernel_ms"] * 1e-3) / 1e12
+    traffic = _traffic_per_launch(dom["block"], dom["ipl"])
+    roofline = {
+        "bound": "alu",
+        "achieved": achieved,
+        "peak": FP64_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": achieved / FP64_PEAK_TFLOPS,
+        "traffic": traffic,
+        "kernel": ("k_eval_f64<2, %d, %d, false>" % (dom["block"], dom["ipl"]) if dom["kind"] == 0
+                   else "k_eval_small<%d, false>" % dom["ipl"]),
+        "launches": dom["launches"],
+        "avg_launch_us": 1e3 * dom["kernel_ms"] / max(1, dom["launches"]),
+        "flops_per_launch": FLOPS_PER_INTERACTION * dom["interactions"] / max(1, dom["launches"]),
+    }
+
+    # accuracy vs the FP64 oracle on sampled targets of the final, synchronised state
+    import oracle
+
+    rng = np.random.Generator(np.random.PCG64(7))
+    idx = np.sort(rng.choice(n, 64, replace=False))
+    F = torch.empty((9, n), dtype=torch.float64, device="cuda")
+    P = sysg.S[0:9].contiguous()
+    act = torch.from_numpy(idx.astype(np.int32)).cuda()
+    sysg.ctx.h6_evaluate(P, sysg.m, act, len(idx), prec, F)
+    torch.cuda.synchronize()
+    xs, vs, as_ = (P[3 * k:3 * k + 3].T.cpu().numpy().copy() for k in range(3))
+    want = oracle.forces(xs, vs, m, eps * eps, a=as_, idx=idx, order=2)[:3]
+    acc = {}
+    for k, name in enumerate("ajs"):
+        got = F[3 * k:3 * k + 3, :len(idx)].T.cpu().numpy()
+        err = np.linalg.norm(got - want[k], axis=1) / np.linalg.norm(want[k], axis=1)
+        acc["max_rel_err_" + name] = float(err.max())
+    acc["sample_targets"] = len(idx)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's a/j/s evaluation of sampled targets against all n sources
+        probe = np.arange(0, n, max(1, n // 256))[:256]
+        tp = time.perf_counter()
+        oracle.forces(xs, vs, m, eps * eps, a=as_, idx=probe, order=2)
+        tp = time.perf_counter() - tp
+        n_i = int(min(n, max(256, len(probe) * args.cpu_seconds / max(tp, 1e-6))))
+        sample = np.sort(rng.choice(n, n_i, replace=False))
+        tc = time.perf_counter()
+        oracle.forces(xs, vs, m, eps * eps, a=as_, idx=sample, order=2)
+        tc = time.perf_counter() - tc
+        cpu = {
+            "value": n_i * n / tc,
+            "unit": "interactions/s",
+            "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "FP64 oracle a/j/s evaluation of %d sampled targets against all %d sources "
+                      "of the final synchronised state (%.1f s)" % (n_i, n, tc),
+        }
+        _log("cpu baseline: %.3e interactions/s on %d threads" % (cpu["value"], cpu["cores"]))
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / max(1, args.steps),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == h6.H6_FP64 else "f64+f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "plummer_n%d_eps1e-4_blocksteps_eta0.4_dtmax1/16_%gtu" % (n, args.steps / 16),
+            "n": n, "eps": eps, "eta": eta, "dt_max": 2.0 ** -lev_min, "lev_max": lev_max,
+            "time_units": args.steps / 16.0, "precision": args.precision, "seed": args.seed,
+            "flops_per_interaction": FLOPS_PER_INTERACTION,
+        },
+        "pct_fp64_vector_peak": 100.0 * value * FLOPS_PER_INTERACTION / (FP64_PEAK_TFLOPS * 1e12),
+        "pct_fp32_vector_peak": 100.0 * value * FLOPS_PER_INTERACTION / (FP32_PEAK_TFLOPS * 1e12),
+        "blocks": blocks,
+        "particle_steps": psteps,
+        "interactions": inter,
+        "eval_kernel_share_of_wall": 1e-3 * eval_ms / wall if wall > 0 else None,
+        "eval_by_active_set": by_active,
+        "energy_rel_err_max": drift,
+        "accuracy": acc,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -115,12 +115,17 @@ int h6_destroy(h6_ctx ctx);
 int h6_set_stream(h6_ctx ctx, void *hip_stream);
 
 /*
- * Launch shape of the evaluation kernels: threads per workgroup (64, 128
- * or 256), targets per thread (1 or 2) and number of source slices the
- * sum is split into (>= 1). 0 keeps the built-in choice for that field.
- * Results agree to rounding for every shape. Errors: H6_EINVAL.
+ * Launch shape of the evaluation. Active sets of at most small_max targets
+ * go to a source-parallel kernel (lanes over sources, no LDS); larger ones
+ * to the LDS-tiled target-parallel kernel with the given threads per
+ * workgroup (64, 128 or 256), targets per thread (1 or 2) and number of
+ * source slices the sum is split into (>= 1). 0 keeps the built-in choice
+ * for block, ipl and n_split; small_max < 0 keeps the built-in threshold and
+ * 0 disables the small-set kernel. Results agree to rounding for every
+ * shape. Errors: H6_EINVAL.
  */
-int h6_set_eval_config(h6_ctx ctx, int block, int ipl, int n_split);
+int h6_set_eval_config(h6_ctx ctx, int block, int ipl, int n_split,
+                       int small_max);
 
 /*
  * Predictor (Sec. 3, first stage): Taylor prediction of all n particles to
@@ -236,6 +241,28 @@ int h6_energy(h6_ctx ctx, const h6_state *st, int64_t n, double out[5]);
  * cleared: H6_OK, H6_EDTMIN or H6_ENONFINITE.
  */
 int h6_check_status(h6_ctx ctx);
+
+/*
+ * Measurement hook: while enabled, HIP events bracket every a/j/s
+ * evaluation kernel the context launches (on its stream), and the event
+ * durations are accumulated per kernel instantiation and per power-of-two
+ * bin of the active-set size. Enabling clears the
+ * records. h6_profile_read (synchronizes) copies up to max records to out
+ * and sets *count. Errors: H6_EINVAL, H6_EHIP.
+ */
+typedef struct {
+    int order;      /* 2: per-step a/j/s; 1, 3: start-up passes */
+    int kind;       /* 0: LDS-tiled kernel; 1: source-parallel small-set kernel */
+    int block, ipl; /* launch shape of the instantiation */
+    int precision;  /* H6_FP64 or H6_MIXED */
+    int nact_log2;  /* bin: floor(log2(n_act)) of the launches in this record */
+    int64_t launches;
+    double interactions; /* sum of n_act * n over the launches */
+    double kernel_ms;    /* sum of the event-measured kernel durations */
+} h6_eval_timing;
+
+int h6_profile_enable(h6_ctx ctx, int on);
+int h6_profile_read(h6_ctx ctx, h6_eval_timing *out, int max, int *count);
 
 /* Text of a return code; text of the context's last failure ("" if none). */
 const char *h6_strerror(int code);

@@ -101,6 +101,61 @@ int read_flags(h6_ctx ctx) {
 
 }  // namespace
 
+namespace h6 {
+
+hipError_t prof_begin(h6_ctx ctx, hipEvent_t *e0, hipEvent_t *e1) {
+    for (hipEvent_t *e : {e0, e1}) {
+        if (!ctx->event_pool.empty()) {
+            *e = ctx->event_pool.back();
+            ctx->event_pool.pop_back();
+        } else {
+            hipError_t r = hipEventCreate(e);
+            if (r != hipSuccess) return r;
+        }
+    }
+    return hipEventRecord(*e0, ctx->stream);
+}
+
+hipError_t prof_end(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int order, const EvalConfig &cfg,
+                    int precision, int64_t n_act, double interactions) {
+    hipError_t r = hipEventRecord(e1, ctx->stream);
+    if (r != hipSuccess) return r;
+    int bin = 0;
+    for (int64_t na = n_act; na > 1; na >>= 1) ++bin;
+    int key = -1;
+    for (size_t q = 0; q < ctx->timings.size(); ++q) {
+        const h6_eval_timing &t = ctx->timings[q];
+        if (t.order == order && t.kind == cfg.kind && t.block == cfg.block && t.ipl == cfg.ipl &&
+            t.precision == precision && t.nact_log2 == bin)
+            key = (int)q;
+    }
+    if (key < 0) {
+        h6_eval_timing t = {order, cfg.kind, cfg.block, cfg.ipl, precision, bin, 0, 0.0, 0.0};
+        ctx->timings.push_back(t);
+        key = (int)ctx->timings.size() - 1;
+    }
+    ctx->pending.push_back({e0, e1, key, interactions});
+    return hipSuccess;
+}
+
+hipError_t prof_resolve(h6_ctx ctx) {
+    for (const auto &p : ctx->pending) {
+        float ms = 0.0f;
+        hipError_t r = hipEventElapsedTime(&ms, p.e0, p.e1);
+        if (r != hipSuccess) return r;
+        h6_eval_timing &t = ctx->timings[p.key];
+        t.launches += 1;
+        t.interactions += p.interactions;
+        t.kernel_ms += ms;
+        ctx->event_pool.push_back(p.e0);
+        ctx->event_pool.push_back(p.e1);
+    }
+    ctx->pending.clear();
+    return hipSuccess;
+}
+
+}  // namespace h6
+
 extern "C" {
 
 const char *h6_strerror(int code) {
@@ -169,6 +224,11 @@ int h6_destroy(h6_ctx ctx) {
     if (ctx->flags) (void)hipFree(ctx->flags);
     if (ctx->ered) (void)hipFree(ctx->ered);
     if (ctx->host) (void)hipHostFree(ctx->host);
+    for (const auto &p : ctx->pending) {
+        (void)hipEventDestroy(p.e0);
+        (void)hipEventDestroy(p.e1);
+    }
+    for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
     delete ctx;
     return H6_OK;
 }
@@ -179,7 +239,7 @@ int h6_set_stream(h6_ctx ctx, void *hip_stream) {
     return H6_OK;
 }
 
-int h6_set_eval_config(h6_ctx ctx, int block, int ipl, int n_split) {
+int h6_set_eval_config(h6_ctx ctx, int block, int ipl, int n_split, int small_max) {
     if (!ctx) return H6_EINVAL;
     if (block != 0 && block != 64 && block != 128 && block != 256)
         return fail_arg(ctx, "block must be 0, 64, 128 or 256");
@@ -188,6 +248,7 @@ int h6_set_eval_config(h6_ctx ctx, int block, int ipl, int n_split) {
     ctx->cfg_block = block;
     ctx->cfg_ipl = ipl;
     ctx->cfg_split = n_split;
+    ctx->cfg_small = small_max < 0 ? -1 : small_max;
     return H6_OK;
 }
 
@@ -307,6 +368,7 @@ int h6_next_block(h6_ctx ctx, const h6_state *st, int64_t n, int32_t *active, in
     H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
     *t_next = h64[0];
     *n_act = h32[0];
+    if (!ctx->pending.empty()) H6_TRY(ctx, prof_resolve(ctx), "profile events");
     return H6_OK;
 }
 
@@ -389,6 +451,30 @@ int h6_energy(h6_ctx ctx, const h6_state *st, int64_t n, double out[5]) {
            "energy readback");
     H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
     std::memcpy(out, h, 5 * sizeof(double));
+    return H6_OK;
+}
+
+int h6_profile_enable(h6_ctx ctx, int on) {
+    if (!ctx) return H6_EINVAL;
+    H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    H6_TRY(ctx, prof_resolve(ctx), "profile events");
+    ctx->timings.clear();
+    ctx->prof = on != 0;
+    return H6_OK;
+}
+
+int h6_profile_read(h6_ctx ctx, h6_eval_timing *out, int max, int *count) {
+    if (!ctx || !count || max < 0 || (max > 0 && !out)) return fail_arg(ctx, "bad profile read");
+    H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    H6_TRY(ctx, prof_resolve(ctx), "profile events");
+    const int nrec = (int)ctx->timings.size();
+    if (nrec > max) {
+        *count = nrec;
+        for (int q = 0; q < max; ++q) out[q] = ctx->timings[q];
+        return H6_OK;
+    }
+    for (int q = 0; q < nrec && q < max; ++q) out[q] = ctx->timings[q];
+    *count = nrec;
     return H6_OK;
 }
 

@@ -71,11 +71,46 @@ __device__ __forceinline__ void two_sum_into(double &hi, double &lo, double x) {
     lo += err;
 }
 
+// Pair terms of order 2 (a, j, s) accumulated into acc[0..8], from the
+// differences source - target r, v, a and the source mass. With
+// R^2 = |r|^2 + eps^2, alpha = r.v/R^2, beta = (v.v + r.a)/R^2 + alpha^2:
+//   A = m r / R^3,  J = m w / R^3 with w = v - 3 alpha r,
+//   S = m u / R^3 with u = a - 6 alpha w - 3 beta r.
+__device__ __forceinline__ void pair_acc2(double dx, double dy, double dz, double dvx, double dvy,
+                                          double dvz, double dax, double day, double daz,
+                                          double r2, double mj, double *acc) {
+    const double rinv = rsqrt_f64(r2);
+    const double rinv2 = rinv * rinv;
+    const double mr3 = (mj * rinv) * rinv2;
+    const double rv = fma(dz, dvz, fma(dy, dvy, dx * dvx));
+    const double alpha = rv * rinv2;
+    const double a3 = 3.0 * alpha;
+    const double wx = fma(-a3, dx, dvx), wy = fma(-a3, dy, dvy), wz = fma(-a3, dz, dvz);
+    const double vvra =
+        fma(dz, daz, fma(dy, day, fma(dx, dax, fma(dvz, dvz, fma(dvy, dvy, dvx * dvx)))));
+    const double beta = fma(alpha, alpha, vvra * rinv2);
+    const double b3 = 3.0 * beta;
+    const double a6 = a3 + a3;
+    const double ux = fma(-a6, wx, fma(-b3, dx, dax));
+    const double uy = fma(-a6, wy, fma(-b3, dy, day));
+    const double uz = fma(-a6, wz, fma(-b3, dz, daz));
+    acc[0] = fma(mr3, dx, acc[0]);
+    acc[1] = fma(mr3, dy, acc[1]);
+    acc[2] = fma(mr3, dz, acc[2]);
+    acc[3] = fma(mr3, wx, acc[3]);
+    acc[4] = fma(mr3, wy, acc[4]);
+    acc[5] = fma(mr3, wz, acc[5]);
+    acc[6] = fma(mr3, ux, acc[6]);
+    acc[7] = fma(mr3, uy, acc[7]);
+    acc[8] = fma(mr3, uz, acc[8]);
+}
+
 // Far, massless padding source: contributes exactly zero.
 constexpr double kPadPos = 1.0e18;
 
 template <int ORDER, int BLOCK, int IPL, bool SKIPSELF>
-__global__ __launch_bounds__(BLOCK) void k_eval_f64(SrcPtrs src, const int32_t *__restrict__ active,
+__global__ __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(IPL == 1 ? 4 : 2))) void k_eval_f64(SrcPtrs src, const int32_t *__restrict__ active,
                                                     int n, int n_act, double eps2, int slice_len,
                                                     OutPtrs out, int64_t slice_stride) {
     using T = Traits<ORDER>;
@@ -170,45 +205,41 @@ __global__ __launch_bounds__(BLOCK) void k_eval_f64(SrcPtrs src, const int32_t *
                     r2 = self ? 1.0 : r2;
                     m_eff = self ? 0.0 : mj;
                 }
-                const double rinv = rsqrt_f64(r2);
-                const double rinv2 = rinv * rinv;
-                const double mr3 = (m_eff * rinv) * rinv2;
-                const double rv = fma(dz, dvz, fma(dy, dvy, dx * dvx));
-                const double alpha = rv * rinv2;
-                const double a3 = 3.0 * alpha;
-                // w = v - 3 alpha r, so that J = mr3 w
-                const double wx = fma(-a3, dx, dvx), wy = fma(-a3, dy, dvy), wz = fma(-a3, dz, dvz);
-                if (ORDER == 1) {
-                    acc[u][0] = fma(mr3, dx, acc[u][0]);
-                    acc[u][1] = fma(mr3, dy, acc[u][1]);
-                    acc[u][2] = fma(mr3, dz, acc[u][2]);
-                    acc[u][3] = fma(mr3, wx, acc[u][3]);
-                    acc[u][4] = fma(mr3, wy, acc[u][4]);
-                    acc[u][5] = fma(mr3, wz, acc[u][5]);
+                if constexpr (ORDER == 2) {
+                    pair_acc2(dx, dy, dz, dvx, dvy, dvz, aj0 - ai[u][0], aj1 - ai[u][1],
+                              aj2 - ai[u][2], r2, m_eff, acc[u]);
                 } else {
-                    const double dax = aj0 - ai[u][0], day = aj1 - ai[u][1], daz = aj2 - ai[u][2];
-                    // v.v + r.a
-                    const double vvra = fma(dz, daz, fma(dy, day, fma(dx, dax,
-                                        fma(dvz, dvz, fma(dvy, dvy, dvx * dvx)))));
-                    const double beta = fma(alpha, alpha, vvra * rinv2);
-                    const double b3 = 3.0 * beta;
-                    const double a6 = a3 + a3;
-                    // u = a - 6 alpha w - 3 beta r, so that S = mr3 u
-                    const double ux = fma(-a6, wx, fma(-b3, dx, dax));
-                    const double uy = fma(-a6, wy, fma(-b3, dy, day));
-                    const double uz = fma(-a6, wz, fma(-b3, dz, daz));
-                    if (ORDER == 2) {
+                    const double rinv = rsqrt_f64(r2);
+                    const double rinv2 = rinv * rinv;
+                    const double mr3 = (m_eff * rinv) * rinv2;
+                    const double rv = fma(dz, dvz, fma(dy, dvy, dx * dvx));
+                    const double alpha = rv * rinv2;
+                    const double a3 = 3.0 * alpha;
+                    // w = v - 3 alpha r, so that J = mr3 w
+                    const double wx = fma(-a3, dx, dvx), wy = fma(-a3, dy, dvy),
+                                 wz = fma(-a3, dz, dvz);
+                    if constexpr (ORDER == 1) {
                         acc[u][0] = fma(mr3, dx, acc[u][0]);
                         acc[u][1] = fma(mr3, dy, acc[u][1]);
                         acc[u][2] = fma(mr3, dz, acc[u][2]);
                         acc[u][3] = fma(mr3, wx, acc[u][3]);
                         acc[u][4] = fma(mr3, wy, acc[u][4]);
                         acc[u][5] = fma(mr3, wz, acc[u][5]);
-                        acc[u][6] = fma(mr3, ux, acc[u][6]);
-                        acc[u][7] = fma(mr3, uy, acc[u][7]);
-                        acc[u][8] = fma(mr3, uz, acc[u][8]);
                     } else {
-                        const double djx = jj0 - ji[u][0], djy = jj1 - ji[u][1], djz = jj2 - ji[u][2];
+                        const double dax = aj0 - ai[u][0], day = aj1 - ai[u][1],
+                                     daz = aj2 - ai[u][2];
+                        const double djx = jj0 - ji[u][0], djy = jj1 - ji[u][1],
+                                     djz = jj2 - ji[u][2];
+                        // v.v + r.a
+                        const double vvra = fma(dz, daz, fma(dy, day, fma(dx, dax,
+                                            fma(dvz, dvz, fma(dvy, dvy, dvx * dvx)))));
+                        const double beta = fma(alpha, alpha, vvra * rinv2);
+                        const double b3 = 3.0 * beta;
+                        const double a6 = a3 + a3;
+                        // u = a - 6 alpha w - 3 beta r, so that S = mr3 u
+                        const double ux = fma(-a6, wx, fma(-b3, dx, dax));
+                        const double uy = fma(-a6, wy, fma(-b3, dy, day));
+                        const double uz = fma(-a6, wz, fma(-b3, dz, daz));
                         const double va = fma(dvz, daz, fma(dvy, day, dvx * dax));
                         const double rj = fma(dz, djz, fma(dy, djy, dx * djx));
                         // gamma = (3 v.a + r.j)/R^2 + alpha (3 beta - 4 alpha^2)
@@ -248,7 +279,18 @@ __global__ __launch_bounds__(BLOCK) void k_eval_f64(SrcPtrs src, const int32_t *
     }
 }
 
-// Compensated (Neumaier) sum of the per-slice partials of each target.
+// Compensated sum of (s1, c1) and (s2, c2): TwoSum of the leading parts,
+// compensations added.
+__device__ __forceinline__ void comp_merge(double &s, double &c, double s2, double c2) {
+    const double t = s + s2;
+    const double bp = t - s;
+    const double err = (s - (t - bp)) + (s2 - bp);
+    s = t;
+    c += err + c2;
+}
+
+// Slice reduction, few slices: one thread per (component, target), a
+// Neumaier sum over the slices with all loads issued up front.
 __global__ __launch_bounds__(256) void k_reduce_slices(const double *__restrict__ partial,
                                                        int64_t ld, int n_split, int ncomp, int out0,
                                                        int n_act, OutPtrs out) {
@@ -258,13 +300,143 @@ __global__ __launch_bounds__(256) void k_reduce_slices(const double *__restrict_
         const int c = (int)(idx / n_act);
         const int k = (int)(idx - (int64_t)c * n_act);
         double s = 0.0, comp = 0.0;
-        for (int sl = 0; sl < n_split; ++sl) {
+        for (int s0 = 0; s0 < n_split; s0 += 8) {
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                x[u] = s0 + u < n_split ? partial[((int64_t)(s0 + u) * ncomp + c) * ld + k] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double t = s + x[u];
+                comp += fabs(s) >= fabs(x[u]) ? (s - t) + x[u] : (x[u] - t) + s;
+                s = t;
+            }
+        }
+        out.p[out0 + c][k] = s + comp;
+    }
+}
+
+// Slice reduction, many slices: one wave per (component, target). Each lane
+// sums every 64th slice (Neumaier), then a fixed butterfly of compensated
+// merges combines the lanes, so the result does not depend on timing.
+__global__ __launch_bounds__(256) void k_reduce_slices_wave(const double *__restrict__ partial,
+                                                            int64_t ld, int n_split, int ncomp,
+                                                            int out0, int n_act, OutPtrs out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t total = (int64_t)ncomp * n_act;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t idx = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); idx < total;
+         idx += waves) {
+        const int c = (int)(idx / n_act);
+        const int k = (int)(idx - (int64_t)c * n_act);
+        double s = 0.0, comp = 0.0;
+        for (int sl = lane; sl < n_split; sl += 64) {
             const double x = partial[((int64_t)sl * ncomp + c) * ld + k];
             const double t = s + x;
             comp += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
             s = t;
         }
-        out.p[out0 + c][k] = s + comp;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double s2 = __shfl_xor(s, off, 64);
+            const double c2 = __shfl_xor(comp, off, 64);
+            // both partners form the same pair in the same order
+            double a = (lane & off) ? s2 : s, ac = (lane & off) ? c2 : comp;
+            const double b = (lane & off) ? s : s2, bc = (lane & off) ? comp : c2;
+            comp_merge(a, ac, b, bc);
+            s = a;
+            comp = ac;
+        }
+        if (lane == 0) out.p[out0 + c][k] = s + comp;
+    }
+}
+
+// Evaluation for small active sets (order 2): the lanes of a wave run over
+// sources (coalesced global loads, no LDS), each wave serving TPW targets
+// whose predicted state is wave-uniform; per-lane sums are flushed into
+// compensated pairs every kSmallFlush sources and combined across lanes by
+// a fixed butterfly. Grid: (one wave per TPW targets) x (source slices).
+constexpr int kSmallFlush = 16;
+
+template <int TPW, bool SKIPSELF>
+__global__ __launch_bounds__(64) void k_eval_small(SrcPtrs src, const int32_t *__restrict__ active,
+                                                    int n, int n_act, double eps2, int slice_len,
+                                                    OutPtrs out, int64_t slice_stride) {
+    const int lane = threadIdx.x;
+    const int wave = blockIdx.x;
+    double xi[TPW][3], vi[TPW][3], ai[TPW][3];
+    int pid[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        int k = wave * TPW + t;
+        k = k < n_act ? k : n_act - 1;
+        const int p = active ? active[k] : k;
+        pid[t] = p;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            xi[t][c] = src.x[c][p];
+            vi[t][c] = src.v[c][p];
+            ai[t][c] = src.a[c][p];
+        }
+    }
+    double acc[TPW][9], hi[TPW][9], lo[TPW][9];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc[t][q] = hi[t][q] = lo[t][q] = 0.0;
+
+    const int jb = (int)blockIdx.y * slice_len;
+    const int je = min(n, jb + slice_len);
+    int since_flush = 0;
+    for (int j = jb + lane; j < je; j += 64) {
+        const double xj0 = src.x[0][j], xj1 = src.x[1][j], xj2 = src.x[2][j];
+        const double vj0 = src.v[0][j], vj1 = src.v[1][j], vj2 = src.v[2][j];
+        const double aj0 = src.a[0][j], aj1 = src.a[1][j], aj2 = src.a[2][j];
+        const double mj = src.m[j];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            const double dx = xj0 - xi[t][0], dy = xj1 - xi[t][1], dz = xj2 - xi[t][2];
+            double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
+            double m_eff = mj;
+            if (SKIPSELF) {
+                const bool self = j == pid[t];
+                r2 = self ? 1.0 : r2;
+                m_eff = self ? 0.0 : mj;
+            }
+            pair_acc2(dx, dy, dz, vj0 - vi[t][0], vj1 - vi[t][1], vj2 - vi[t][2], aj0 - ai[t][0],
+                      aj1 - ai[t][1], aj2 - ai[t][2], r2, m_eff, acc[t]);
+        }
+        if (++since_flush == kSmallFlush) {
+            since_flush = 0;
+#pragma unroll
+            for (int t = 0; t < TPW; ++t)
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    two_sum_into(hi[t][q], lo[t][q], acc[t][q]);
+                    acc[t][q] = 0.0;
+                }
+        }
+    }
+    const int64_t soff = (int64_t)blockIdx.y * slice_stride;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            two_sum_into(hi[t][q], lo[t][q], acc[t][q]);
+            double sv = hi[t][q], cv = lo[t][q];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double s2 = __shfl_xor(sv, off, 64);
+                const double c2 = __shfl_xor(cv, off, 64);
+                double a = (lane & off) ? s2 : sv, ac = (lane & off) ? c2 : cv;
+                const double b = (lane & off) ? sv : s2, bc = (lane & off) ? cv : c2;
+                comp_merge(a, ac, b, bc);
+                sv = a;
+                cv = ac;
+            }
+            const int k = wave * TPW + t;
+            if (lane == 0 && k < n_act) out.p[q][soff + k] = sv + cv;
+        }
     }
 }
 
@@ -289,7 +461,7 @@ hipError_t dispatch_shape(const EvalConfig &cfg, bool skipself, dim3 grid, hipSt
     if (cfg.block == B && cfg.ipl == I)                                                         \
         return dispatch_f64<ORDER, B, I>(skipself, grid, st, src, active, n, n_act, eps2,     \
                                          slice_len, out, slice_stride);
-    if (ORDER == 2) {
+    if constexpr (ORDER == 2) {
         H6_SHAPE(64, 1)
         H6_SHAPE(128, 1)
         H6_SHAPE(256, 1)
@@ -305,17 +477,64 @@ hipError_t dispatch_shape(const EvalConfig &cfg, bool skipself, dim3 grid, hipSt
 
 int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+hipError_t dispatch_small(int tpw, bool skipself, dim3 grid, hipStream_t st, const SrcPtrs &src,
+                          const int32_t *active, int n, int n_act, double eps2, int slice_len,
+                          const OutPtrs &out, int64_t slice_stride) {
+#define H6_SMALL(T)                                                                            \
+    if (tpw == T) {                                                                            \
+        if (skipself)                                                                          \
+            hipLaunchKernelGGL((k_eval_small<T, true>), grid, dim3(64), 0, st, src, active, n, \
+                               n_act, eps2, slice_len, out, slice_stride);                     \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_eval_small<T, false>), grid, dim3(64), 0, st, src, active, n,\
+                               n_act, eps2, slice_len, out, slice_stride);                     \
+        return hipGetLastError();                                                              \
+    }
+    H6_SMALL(1)
+    H6_SMALL(2)
+    H6_SMALL(4)
+#undef H6_SMALL
+    return hipErrorInvalidValue;
+}
+
+// Above this many slices the reduction gives each output a whole wave.
+constexpr int kWaveReduceMinSplit = 24;
+// Active sets up to this size use the source-parallel kernel by default.
+constexpr int kDefaultSmallMax = 32;
+// Waves a launch aims to put in flight (256 CUs x 4 SIMDs x 2).
+constexpr int kTargetWaves = 2048;
+// Shortest source slice of the source-parallel kernel (4 sources per lane).
+constexpr int kSmallMinSlice = 256;
+
 }  // namespace
 
 EvalConfig choose_eval_config(h6_ctx ctx, int order, int precision, int n, int n_act) {
     (void)precision;
     EvalConfig cfg;
+    const int small_max = ctx->cfg_small >= 0 ? ctx->cfg_small : kDefaultSmallMax;
+    if (order == 2 && n_act <= small_max) {
+        // source-parallel kernel: one wave per TPW targets
+        cfg.kind = 1;
+        cfg.block = 64;
+        cfg.ipl = n_act <= 4 ? 1 : 2;
+        const int waves_i = ceil_div(n_act, cfg.ipl);
+        int split = ceil_div(kTargetWaves, waves_i);
+        const int max_split = ceil_div(n, kSmallMinSlice);
+        if (split > max_split) split = max_split;
+        const int64_t cap_split = ctx->partial_cap / ((int64_t)9 * n_act);
+        if (split > cap_split) split = (int)cap_split;
+        cfg.n_split = split < 1 ? 1 : split;
+        return cfg;
+    }
+    cfg.kind = 0;
     if (order != 2) {
         cfg.block = 256;
         cfg.ipl = 1;
     } else {
-        cfg.block = ctx->cfg_block ? ctx->cfg_block : (n_act <= 2048 ? 64 : 256);
-        cfg.ipl = ctx->cfg_ipl ? ctx->cfg_ipl : 1;
+        // measured on gfx950 at N = 65536: one target per lane in 64-thread
+        // workgroups up to 512 targets, two per lane beyond
+        cfg.block = ctx->cfg_block ? ctx->cfg_block : (n_act <= 16384 ? 64 : 256);
+        cfg.ipl = ctx->cfg_ipl ? ctx->cfg_ipl : (n_act <= 512 ? 1 : 2);
     }
     const int per_block = cfg.block * cfg.ipl;
     const int blocks_i = ceil_div(n_act, per_block);
@@ -323,11 +542,12 @@ EvalConfig choose_eval_config(h6_ctx ctx, int order, int precision, int n, int n
     if (ctx->cfg_split && order == 2) {
         split = ctx->cfg_split;
     } else {
-        // aim at about 8 workgroups per CU on 256 CUs
-        const int target = 2048;
-        split = ceil_div(target, blocks_i);
+        // about kTargetWaves waves in flight on 256 CUs
+        split = ceil_div((int64_t)kTargetWaves * 64, (int64_t)blocks_i * cfg.block);
+        // each slice holds at least four tiles of sources
+        const int max_split = ceil_div(n, 4 * cfg.block);
+        if (split > max_split) split = max_split;
     }
-    // each slice holds at least one tile of sources
     const int max_by_tiles = ceil_div(n, cfg.block);
     if (split > max_by_tiles) split = max_by_tiles;
     if (split < 1) split = 1;
@@ -345,7 +565,7 @@ hipError_t launch_eval(h6_ctx ctx, int order, int precision, const SrcPtrs &src,
     EvalConfig cfg = choose_eval_config(ctx, order, precision, n, n_act);
     // equal slices, each a whole number of tiles
     int slice_len = ceil_div(n, cfg.n_split);
-    slice_len = ceil_div(slice_len, cfg.block) * cfg.block;
+    slice_len = ceil_div(slice_len, cfg.block) * cfg.block;  // whole tiles (64 for kind 1)
     cfg.n_split = ceil_div(n, slice_len);
     if (used) *used = cfg;
 
@@ -364,8 +584,17 @@ hipError_t launch_eval(h6_ctx ctx, int order, int precision, const SrcPtrs &src,
         for (int c = 0; c < ncomp; ++c) dst.p[out0 + c] = ctx->partial + (int64_t)c * n_act;
         slice_stride = (int64_t)ncomp * n_act;
     }
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (ctx->prof) {
+        hipError_t pe = prof_begin(ctx, &ev0, &ev1);
+        if (pe != hipSuccess) return pe;
+    }
     hipError_t e;
-    if (order == 1)
+    if (cfg.kind == 1) {
+        dim3 g(ceil_div(n_act, cfg.ipl), cfg.n_split);
+        e = dispatch_small(cfg.ipl, skipself, g, ctx->stream, src, active, n, n_act, ctx->eps2,
+                           slice_len, dst, slice_stride);
+    } else if (order == 1)
         e = dispatch_shape<1>(cfg, skipself, grid, ctx->stream, src, active, n, n_act, ctx->eps2,
                               slice_len, dst, slice_stride);
     else if (order == 2)
@@ -374,12 +603,21 @@ hipError_t launch_eval(h6_ctx ctx, int order, int precision, const SrcPtrs &src,
     else
         e = dispatch_shape<3>(cfg, skipself, grid, ctx->stream, src, active, n, n_act, ctx->eps2,
                               slice_len, dst, slice_stride);
+    if (e == hipSuccess && ctx->prof)
+        e = prof_end(ctx, ev0, ev1, order, cfg, precision, n_act, (double)n_act * (double)n);
     if (e != hipSuccess || cfg.n_split == 1) return e;
     const int64_t total = (int64_t)ncomp * n_act;
-    int rb = ceil_div(total, 256);
-    if (rb > 4096) rb = 4096;
-    hipLaunchKernelGGL(k_reduce_slices, dim3(rb), dim3(256), 0, ctx->stream, ctx->partial,
-                       (int64_t)n_act, cfg.n_split, ncomp, out0, n_act, out);
+    if (cfg.n_split >= kWaveReduceMinSplit) {
+        int rb = ceil_div(total, 4);
+        if (rb > 8192) rb = 8192;
+        hipLaunchKernelGGL(k_reduce_slices_wave, dim3(rb), dim3(256), 0, ctx->stream, ctx->partial,
+                           (int64_t)n_act, cfg.n_split, ncomp, out0, n_act, out);
+    } else {
+        int rb = ceil_div(total, 256);
+        if (rb > 4096) rb = 4096;
+        hipLaunchKernelGGL(k_reduce_slices, dim3(rb), dim3(256), 0, ctx->stream, ctx->partial,
+                           (int64_t)n_act, cfg.n_split, ncomp, out0, n_act, out);
+    }
     return hipGetLastError();
 }
 

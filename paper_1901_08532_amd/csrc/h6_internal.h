@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "h6.h"
 
@@ -31,8 +32,9 @@ struct OutPtrs {
 };
 
 struct EvalConfig {
+    int kind;    // 0: LDS-tiled target-parallel kernel; 1: source-parallel small-set kernel
     int block;   // threads per workgroup
-    int ipl;     // targets per thread
+    int ipl;     // targets per thread (kind 0) or per wave (kind 1)
     int n_split; // source slices
 };
 
@@ -44,6 +46,7 @@ struct h6_ctx_s {
     hipStream_t stream = nullptr;
     int device = 0;
     int cfg_block = 0, cfg_ipl = 0, cfg_split = 0;  // 0: automatic
+    int cfg_small = -1;                             // < 0: built-in threshold
     // scratch (device)
     double *partial = nullptr;     // [n_split][ncomp][ld] partial sums
     int64_t partial_cap = 0;       // doubles
@@ -56,6 +59,16 @@ struct h6_ctx_s {
     // pinned host staging for scheduler/energy readback
     void *host = nullptr;
     std::string last_error;
+    // measurement hook (h6_profile_enable)
+    struct PendingTiming {
+        hipEvent_t e0, e1;
+        int key;
+        double interactions;
+    };
+    bool prof = false;
+    std::vector<hipEvent_t> event_pool;
+    std::vector<PendingTiming> pending;
+    std::vector<h6_eval_timing> timings;
 };
 
 namespace h6 {
@@ -77,6 +90,11 @@ hipError_t launch_next_block(h6_ctx ctx, const h6_state *st, int n, int32_t *act
 hipError_t launch_energy(h6_ctx ctx, const h6_state *st, int n);
 
 int sched_blocks_for(int64_t n);
+// Measurement hook helpers (api.hip).
+hipError_t prof_begin(h6_ctx ctx, hipEvent_t *e0, hipEvent_t *e1);
+hipError_t prof_end(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int order, const EvalConfig &cfg,
+                    int precision, int64_t n_act, double interactions);
+hipError_t prof_resolve(h6_ctx ctx);  // stream must be idle
 int energy_blocks_for(int64_t n);
 
 }  // namespace h6

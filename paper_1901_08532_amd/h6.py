@@ -52,6 +52,12 @@ class h6_run_stats(C.Structure):
                 ("interactions", C.c_double), ("t_end", C.c_int64)]
 
 
+class h6_eval_timing(C.Structure):
+    _fields_ = [("order", C.c_int), ("kind", C.c_int), ("block", C.c_int), ("ipl", C.c_int),
+                ("precision", C.c_int), ("nact_log2", C.c_int),
+                ("launches", C.c_int64), ("interactions", C.c_double), ("kernel_ms", C.c_double)]
+
+
 class H6Error(RuntimeError):
     def __init__(self, code, where, detail=""):
         self.code = code
@@ -66,7 +72,7 @@ _SIGS = {
     "h6_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int64, C.c_double, C.c_void_p]),
     "h6_destroy": (C.c_int, [C.c_void_p]),
     "h6_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
-    "h6_set_eval_config": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
+    "h6_set_eval_config": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int]),
     "h6_predict": (C.c_int, [C.c_void_p, C.POINTER(h6_state), C.c_int64, C.c_int64,
                              C.POINTER(h6_pred)]),
     "h6_predict_dt": (C.c_int, [C.c_void_p, C.POINTER(h6_state), C.c_int64, C.c_double,
@@ -92,6 +98,9 @@ _SIGS = {
                                   C.POINTER(h6_force), C.c_double, C.c_int64, C.c_int]),
     "h6_energy": (C.c_int, [C.c_void_p, C.POINTER(h6_state), C.c_int64, C.POINTER(C.c_double)]),
     "h6_check_status": (C.c_int, [C.c_void_p]),
+    "h6_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "h6_profile_read": (C.c_int, [C.c_void_p, C.POINTER(h6_eval_timing), C.c_int,
+                                  C.POINTER(C.c_int)]),
     "h6_strerror": (C.c_char_p, [C.c_int]),
     "h6_last_error": (C.c_char_p, [C.c_void_p]),
 }
@@ -196,9 +205,9 @@ class Context:
     def set_stream(self, stream: torch.cuda.Stream):
         self._check(lib().h6_set_stream(self._h, C.c_void_p(stream.cuda_stream)), "h6_set_stream")
 
-    def set_eval_config(self, block=0, ipl=0, n_split=0):
-        self._check(lib().h6_set_eval_config(self._h, int(block), int(ipl), int(n_split)),
-                    "h6_set_eval_config")
+    def set_eval_config(self, block=0, ipl=0, n_split=0, small_max=-1):
+        self._check(lib().h6_set_eval_config(self._h, int(block), int(ipl), int(n_split),
+                                             int(small_max)), "h6_set_eval_config")
 
     # ---- single stages -------------------------------------------------
     def h6_evaluate(self, P, m, active, n_act, precision, F):
@@ -282,6 +291,18 @@ class Context:
 
     def h6_check_status(self):
         return lib().h6_check_status(self._h)
+
+    def h6_profile_enable(self, on=True):
+        self._check(lib().h6_profile_enable(self._h, 1 if on else 0), "h6_profile_enable")
+
+    def h6_profile_read(self):
+        """List of dicts, one per evaluation-kernel instantiation launched."""
+        cap = 1024
+        buf = (h6_eval_timing * cap)()
+        cnt = C.c_int()
+        self._check(lib().h6_profile_read(self._h, buf, cap, C.byref(cnt)), "h6_profile_read")
+        return [{k: getattr(buf[q], k) for k, _ in h6_eval_timing._fields_}
+                for q in range(min(cnt.value, cap))]
 
 
 class System:

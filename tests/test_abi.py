@@ -50,7 +50,7 @@ def test_null_context_and_bad_create_arguments():
     assert L.h6_evaluate(None, None, None, 1, None, 1, 0, None) == h6.H6_EINVAL
     assert L.h6_energy(None, C.byref(st), 1, None) == h6.H6_EINVAL
     assert L.h6_check_status(None) == h6.H6_EINVAL
-    assert L.h6_set_eval_config(None, 64, 1, 1) == h6.H6_EINVAL
+    assert L.h6_set_eval_config(None, 64, 1, 1, -1) == h6.H6_EINVAL
 
 
 def test_missing_library_fails_loudly(monkeypatch):

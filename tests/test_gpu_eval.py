@@ -79,6 +79,36 @@ def test_launch_shapes_agree_and_are_deterministic(block, ipl, split):
     _check(got1, want)
 
 
+@pytest.mark.parametrize("n_act", [1, 2, 3, 5, 8, 13, 32, 33])
+@pytest.mark.parametrize("small_max", [0, 64])
+def test_small_active_sets_both_kernels(n_act, small_max):
+    # small_max 64: source-parallel kernel; 0: LDS-tiled kernel with many slices
+    n = 5000
+    x, v, a, m = plummer_pred(n, 200 + n_act, EPS ** 2)
+    rng = np.random.Generator(np.random.PCG64(300 + n_act))
+    act = rng.choice(n, n_act, replace=False).astype(np.int32)  # unsorted on purpose
+    ctx = h6.Context(n, EPS)
+    ctx.set_eval_config(small_max=small_max)
+    got = gpu_evaluate(ctx, x, v, a, m, active=act)
+    again = gpu_evaluate(ctx, x, v, a, m, active=act)
+    for g1, g2 in zip(got, again):
+        assert np.array_equal(g1, g2)
+    want = oracle.forces(x, v, m, EPS ** 2, a=a, idx=act.astype(np.int64), order=2)[:3]
+    _check(got, want)
+
+
+def test_small_kernel_zero_softening():
+    n = 3000
+    x, v, a, _ = plummer_pred(n, 33, 0.0)
+    from paper_1901_08532_amd import ics
+    m = ics.salpeter_masses(n, 34)
+    act = np.array([0, 1, 2999, 1500, 7], dtype=np.int32)
+    ctx = h6.Context(n, 0.0)
+    got = gpu_evaluate(ctx, x, v, a, m, active=act)
+    want = oracle.forces(x, v, m, 0.0, a=a, idx=act.astype(np.int64), order=2)[:3]
+    _check(got, want)
+
+
 def test_empty_active_set_is_noop():
     n = 100
     x, v, a, m = plummer_pred(n, 41, EPS ** 2)
