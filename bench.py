@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -90,6 +92,14 @@ def main():
     from paper_1901_08532_amd import h6, ics
 
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        _log("copy calibration: %d bytes" % nbytes)
+        del src, dst
     n, eps, eta, lev_min, lev_max = args.n, 1e-4, 0.4, 4, 30
     prec = h6.H6_FP64 if args.precision == "fp64" else h6.H6_MIXED
     sync_ticks = 1 << (h6.TICK_BITS - lev_min)

@@ -1,0 +1,111 @@
+"""Summaries of rocprofv3 CSV output for the measurement records.
+
+  python -m paper_1901_08532_amd.profsum stats <kernel_stats.csv> [--match SUBSTR]
+      per-kernel calls, average and total duration
+
+  python -m paper_1901_08532_amd.profsum traffic <fetch counter_collection.csv>
+      <write counter_collection.csv> --copy-bytes B [--match SUBSTR]
+      HBM bytes per dispatch of each matching kernel from FETCH_SIZE and
+      WRITE_SIZE (KiB per dispatch), each scaled by the ratio of the known
+      bytes a plain device copy of B bytes moves to what the same counter
+      reports for it. Prints key = value lines.
+"""
+
+import argparse
+import csv
+import hashlib
+import os
+import re
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+EVAL_SOURCE = os.path.join(ROOT, "paper_1901_08532_amd", "csrc", "eval.hip")
+
+
+def _short(name):
+    name = re.sub(r"\(anonymous namespace\)::", "", name)
+    name = re.sub(r"\(.*\)$", "", name)  # drop the parameter list
+    return name.replace("void ", "").strip()
+
+
+def stats(path, match=None):
+    rows = list(csv.DictReader(open(path)))
+    out = []
+    for r in rows:
+        nm = _short(r["Name"])
+        if match and match not in nm:
+            continue
+        out.append((nm, int(r["Calls"]), float(r["AverageNs"]), float(r["TotalDurationNs"]),
+                    float(r["Percentage"])))
+    out.sort(key=lambda t: -t[3])
+    print("%-60s %8s %14s %14s %7s" % ("kernel", "calls", "avg_us", "total_ms", "pct"))
+    for nm, calls, avg, tot, pct in out:
+        print("%-60s %8d %14.3f %14.3f %7.2f" % (nm[:60], calls, avg / 1e3, tot / 1e6, pct))
+
+
+def _counter_per_dispatch(path, counter):
+    """{kernel short name: [value per dispatch]} for one counter (summed over
+    the per-instance rows of a dispatch)."""
+    per = defaultdict(float)
+    names = {}
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name") != counter:
+            continue
+        d = r["Dispatch_Id"]
+        per[d] += float(r["Counter_Value"])
+        names[d] = _short(r["Kernel_Name"])
+    by_kernel = defaultdict(list)
+    for d, v in per.items():
+        by_kernel[names[d]].append(v)
+    return by_kernel
+
+
+def traffic(fetch_csv, write_csv, copy_bytes, match=None):
+    fetch = _counter_per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = _counter_per_dispatch(write_csv, "WRITE_SIZE")
+    # the calibration copy is the largest dispatch of a copy kernel in each run
+    cf = max(max(v) for k, v in fetch.items() if "copy" in k.lower())
+    cw = max(max(v) for k, v in write.items() if "copy" in k.lower())
+    f_scale = copy_bytes / (cf * 1024.0)
+    w_scale = copy_bytes / (cw * 1024.0)
+    print("# rocprofv3 FETCH_SIZE / WRITE_SIZE, KiB per dispatch, scaled by a %d-byte copy" % copy_bytes)
+    print("copy_fetch_kib = %.1f" % cf)
+    print("copy_write_kib = %.1f" % cw)
+    print("fetch_scale = %.6f" % f_scale)
+    print("write_scale = %.6f" % w_scale)
+    print("eval_source_sha256 = %s" % hashlib.sha256(open(EVAL_SOURCE, "rb").read()).hexdigest())
+    for k in sorted(fetch):
+        if match and match not in k:
+            continue
+        fv = fetch[k]
+        wv = write.get(k, [0.0])
+        fb = sum(fv) / len(fv) * 1024.0 * f_scale
+        wb = sum(wv) / len(wv) * 1024.0 * w_scale
+        m = re.search(r"k_eval_f64<2, (\d+), (\d+), false>", k)
+        tag = "b%s_i%s" % (m.group(1), m.group(2)) if m else re.sub(r"\W+", "_", k)[:60]
+        print("# %s: %d dispatches" % (k, len(fv)))
+        print("fetch_bytes_per_launch_%s = %.1f" % (tag, fb))
+        print("write_bytes_per_launch_%s = %.1f" % (tag, wb))
+        print("hbm_bytes_per_launch_%s = %.1f" % (tag, fb + wb))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("csv")
+    a.add_argument("--match")
+    b = sub.add_parser("traffic")
+    b.add_argument("fetch_csv")
+    b.add_argument("write_csv")
+    b.add_argument("--copy-bytes", type=int, required=True)
+    b.add_argument("--match")
+    args = ap.parse_args()
+    if args.cmd == "stats":
+        stats(args.csv, args.match)
+    else:
+        traffic(args.fetch_csv, args.write_csv, args.copy_bytes, args.match)
+
+
+if __name__ == "__main__":
+    main()
