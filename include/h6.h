@@ -243,6 +243,55 @@ int h6_energy(h6_ctx ctx, const h6_state *st, int64_t n, double out[5]);
 int h6_check_status(h6_ctx ctx);
 
 /*
+ * ---- Adjoint (reverse mode) of the shared-step path ----
+ * Cotangent arrays use the same structures as the forward values. For a
+ * loss L, "cotangent of y" means dL/dy. These calls give gradients of a
+ * loss on the final state with respect to the initial x, v and masses,
+ * through the start-up passes and unrolled shared steps (the caller keeps
+ * checkpoints and replays steps forward as needed).
+ */
+
+/*
+ * VJP of h6_evaluate over all n targets (active = all): from the predicted
+ * sources src, masses m and the cotangents cot (length n) of the evaluated
+ * a, j, s, writes the cotangents of the predicted x, v, a to grad_src
+ * (overwritten) and ADDS the cotangent of the masses to grad_m. The sum is
+ * the hand reversal of the pair terms, gathered over the same pairs as the
+ * forward sum (no atomics). Errors: H6_EINVAL.
+ */
+int h6_evaluate_vjp(h6_ctx ctx, const h6_pred *src, const double *m, int64_t n,
+                    const h6_force *cot, const h6_pred *grad_src,
+                    double *grad_m);
+
+/*
+ * Transpose of h6_correct_shared over step dt. On entry cot holds the
+ * cotangents of the corrected state (x, v, a, j, s, c); on return it holds
+ * those of the state before the step (x, v, a, j, s; c set to 0, the old
+ * crackle entering only the predictor), and cot_force those of the
+ * evaluated a, j, s. cot->m, t, dt are not used. Errors: H6_EINVAL.
+ */
+int h6_correct_shared_vjp(h6_ctx ctx, h6_state *cot, int64_t n,
+                          const h6_force *cot_force, double dt);
+
+/*
+ * Transpose of h6_predict_dt over interval dt: ADDS to the state cotangents
+ * (x, v, a, j, s, c) the contribution of the cotangents cot_pred of the
+ * predicted x, v, a. Errors: H6_EINVAL.
+ */
+int h6_predict_dt_vjp(h6_ctx ctx, h6_state *cot, int64_t n,
+                      const h6_pred *cot_pred, double dt);
+
+/*
+ * VJP of h6_init_forces at the state st (x, v, m and the a, j it produced).
+ * On entry cot holds the cotangents of a, j, s, c at t = 0; the call ADDS
+ * the resulting cotangents of x, v and the masses (cot->m) into cot, and
+ * uses cot->a, cot->j as work space (their pass-2 contributions are added
+ * before pass 1 is reversed). Errors: H6_EINVAL.
+ */
+int h6_init_forces_vjp(h6_ctx ctx, const h6_state *st, int64_t n,
+                       h6_state *cot);
+
+/*
  * Measurement hook: while enabled, HIP events bracket every a/j/s
  * evaluation kernel the context launches (on its stream), and the event
  * durations are accumulated per kernel instantiation and per power-of-two

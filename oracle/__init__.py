@@ -49,6 +49,8 @@ def lib():
         L.orc_forces.argtypes = [C.c_int64, dp, dp, dp, dp, dp, C.c_double, C.c_int64, ip, C.c_int,
                                  dp, dp, dp, dp]
         L.orc_forces.restype = C.c_int
+        L.orc_forces_abs.argtypes = L.orc_forces.argtypes
+        L.orc_forces_abs.restype = C.c_int
         L.orc_predict.argtypes = [C.c_int64] + [dp] * 10
         L.orc_predict.restype = None
         L.orc_correct.argtypes = [C.c_int64] + [dp] * 14
@@ -110,11 +112,11 @@ def pair(r, v, a, jr, m, eps2, order=3):
     return tuple(out)
 
 
-def forces(x, v, m, eps2, a=None, jk=None, idx=None, order=2):
+def forces(x, v, m, eps2, a=None, jk=None, idx=None, order=2, absolute=False):
     """Sums over j != i of the pair terms for targets idx (default: all).
 
     Returns (A, J, S, C) arrays of shape (n_i, 3); S is None for order 1 and
-    C is None below order 3.
+    C is None below order 3. absolute=True sums |pair term| per component.
     """
     x, v, m = _v(x), _v(v), _v(m)
     n = x.shape[0]
@@ -127,7 +129,8 @@ def forces(x, v, m, eps2, a=None, jk=None, idx=None, order=2):
     J = np.zeros((n_i, 3))
     S = np.zeros((n_i, 3)) if order >= 2 else None
     Cc = np.zeros((n_i, 3)) if order >= 3 else None
-    rc = lib().orc_forces(n, _d(x), _d(v), _d(_v(a)) if a is not None else None,
+    fn = lib().orc_forces_abs if absolute else lib().orc_forces
+    rc = fn(n, _d(x), _d(v), _d(_v(a)) if a is not None else None,
                           _d(_v(jk)) if jk is not None else None, _d(m), float(eps2), n_i, _i(ip),
                           int(order), _d(A), _d(J), _d(S), _d(Cc))
     if rc:

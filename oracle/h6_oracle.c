@@ -133,10 +133,40 @@ void orc_pair(const double r[3], const double v[3], const double a[3],
  * Outputs A, J (and S, C by order) are [n_i][3].
  * Returns 0, or -1 on bad arguments.
  */
+static int forces_impl(int64_t n, const double *x, const double *v,
+                       const double *a, const double *jk, const double *m,
+                       double eps2, int64_t n_i, const int64_t *idx, int order,
+                       int absolute, double *A, double *J, double *S,
+                       double *C);
+
 int orc_forces(int64_t n, const double *x, const double *v, const double *a,
                const double *jk, const double *m, double eps2, int64_t n_i,
                const int64_t *idx, int order, double *A, double *J,
                double *S, double *C)
+{
+    return forces_impl(n, x, v, a, jk, m, eps2, n_i, idx, order, 0, A, J, S,
+                       C);
+}
+
+/*
+ * Same sums of |pair term| per component: sum_j |A_ij|, sum_j |J_ij|, ...
+ * The scale against which the rounding error of a sum is measured (a sum
+ * evaluated with unit roundoff u is off by at most about n u times it).
+ */
+int orc_forces_abs(int64_t n, const double *x, const double *v,
+                   const double *a, const double *jk, const double *m,
+                   double eps2, int64_t n_i, const int64_t *idx, int order,
+                   double *A, double *J, double *S, double *C)
+{
+    return forces_impl(n, x, v, a, jk, m, eps2, n_i, idx, order, 1, A, J, S,
+                       C);
+}
+
+static int forces_impl(int64_t n, const double *x, const double *v,
+                       const double *a, const double *jk, const double *m,
+                       double eps2, int64_t n_i, const int64_t *idx, int order,
+                       int absolute, double *A, double *J, double *S,
+                       double *C)
 {
     if (n < 0 || n_i < 0 || !x || !v || !m || !A || !J || order < 1
         || order > 3)
@@ -171,12 +201,12 @@ int orc_forces(int64_t n, const double *x, const double *v, const double *a,
             orc_pair(r, dv, order >= 2 ? da : zero3, order >= 3 ? dj : zero3,
                      m[jj], eps2, order, pA, pJ, pS, pC);
             for (int c = 0; c < 3; c++) {
-                cs_add(&sum[c], pA[c]);
-                cs_add(&sum[3 + c], pJ[c]);
+                cs_add(&sum[c], absolute ? fabs(pA[c]) : pA[c]);
+                cs_add(&sum[3 + c], absolute ? fabs(pJ[c]) : pJ[c]);
                 if (order >= 2)
-                    cs_add(&sum[6 + c], pS[c]);
+                    cs_add(&sum[6 + c], absolute ? fabs(pS[c]) : pS[c]);
                 if (order >= 3)
-                    cs_add(&sum[9 + c], pC[c]);
+                    cs_add(&sum[9 + c], absolute ? fabs(pC[c]) : pC[c]);
             }
         }
         for (int c = 0; c < 3; c++) {

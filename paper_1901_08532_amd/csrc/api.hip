@@ -79,7 +79,7 @@ SrcPtrs src_from_pred(const h6_pred *p, const double *m) {
 
 OutPtrs out_from_force(const h6_force *f) {
     OutPtrs o;
-    for (int c = 0; c < 12; ++c) o.p[c] = nullptr;
+    for (int c = 0; c < kMaxOut; ++c) o.p[c] = nullptr;
     for (int c = 0; c < 3; ++c) {
         o.p[c] = f->a[c];
         o.p[3 + c] = f->j[c];
@@ -89,7 +89,7 @@ OutPtrs out_from_force(const h6_force *f) {
 }
 
 int read_flags(h6_ctx ctx) {
-    int32_t *h = (int32_t *)ctx->host;
+    int32_t *h = (int32_t *)((char *)ctx->host + 64);
     H6_TRY(ctx, hipMemcpyAsync(h, ctx->flags, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream),
            "flag readback");
     H6_TRY(ctx, hipMemsetAsync(ctx->flags, 0, sizeof(int32_t), ctx->stream), "flag reset");
@@ -184,10 +184,14 @@ int h6_create(h6_ctx *out, int64_t n_max, double eps, void *hip_stream) {
     ctx->eps2 = eps * eps;
     ctx->stream = (hipStream_t)hip_stream;
     hipError_t e = hipGetDevice(&ctx->device);
+    int n_cu = 0;
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device);
     if (e != hipSuccess) {
         delete ctx;
         return H6_EHIP;
     }
+    ctx->n_cu = n_cu > 0 ? n_cu : 256;
     // partial sums: n_split * ncomp * n_act doubles, n_split * n_act <= cap
     const int64_t cap_pairs = std::max<int64_t>(2 * n_max, (int64_t)1 << 21);
     ctx->partial_cap = 9 * cap_pairs;
@@ -319,7 +323,7 @@ int h6_init_forces(h6_ctx ctx, h6_state *st, int64_t n) {
     }
     s1.m = st->m;
     OutPtrs o1;
-    for (int c = 0; c < 12; ++c) o1.p[c] = nullptr;
+    for (int c = 0; c < kMaxOut; ++c) o1.p[c] = nullptr;
     for (int c = 0; c < 3; ++c) {
         o1.p[c] = st->a[c];
         o1.p[3 + c] = st->j[c];
@@ -332,7 +336,7 @@ int h6_init_forces(h6_ctx ctx, h6_state *st, int64_t n) {
         s2.j[c] = st->j[c];
     }
     OutPtrs o2;
-    for (int c = 0; c < 12; ++c) o2.p[c] = nullptr;
+    for (int c = 0; c < kMaxOut; ++c) o2.p[c] = nullptr;
     for (int c = 0; c < 3; ++c) {
         o2.p[6 + c] = st->s[c];
         o2.p[9 + c] = st->c[c];
@@ -359,15 +363,12 @@ int h6_next_block(h6_ctx ctx, const h6_state *st, int64_t n, int32_t *active, in
     if (int rc = check_n(ctx, n)) return rc;
     H6_TRY(ctx, launch_next_block(ctx, st, (int)n, active), "next block");
     int64_t *h64 = (int64_t *)ctx->host;
-    int32_t *h32 = (int32_t *)((char *)ctx->host + 64);
     H6_TRY(ctx,
-           hipMemcpyAsync(h64, ctx->sched64 + 1, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream),
-           "t_next readback");
-    H6_TRY(ctx, hipMemcpyAsync(h32, ctx->sched32, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream),
-           "n_act readback");
+           hipMemcpyAsync(h64, ctx->sched64, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream),
+           "block readback");
     H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
     *t_next = h64[0];
-    *n_act = h32[0];
+    *n_act = h64[1];
     if (!ctx->pending.empty()) H6_TRY(ctx, prof_resolve(ctx), "profile events");
     return H6_OK;
 }
@@ -451,6 +452,101 @@ int h6_energy(h6_ctx ctx, const h6_state *st, int64_t n, double out[5]) {
            "energy readback");
     H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
     std::memcpy(out, h, 5 * sizeof(double));
+    return H6_OK;
+}
+
+int h6_evaluate_vjp(h6_ctx ctx, const h6_pred *src, const double *m, int64_t n,
+                    const h6_force *cot, const h6_pred *grad_src, double *grad_m) {
+    if (!ctx) return H6_EINVAL;
+    if (!pred_ok(src) || !m || !force_ok(cot) || !pred_ok(grad_src) || !grad_m)
+        return fail_arg(ctx, "null array");
+    if (int rc = check_n(ctx, n)) return rc;
+    const double *g[9];
+    for (int c = 0; c < 3; ++c) {
+        g[c] = cot->a[c];
+        g[3 + c] = cot->j[c];
+        g[6 + c] = cot->s[c];
+    }
+    OutPtrs o;
+    for (int c = 0; c < kMaxOut; ++c) o.p[c] = nullptr;
+    for (int c = 0; c < 3; ++c) {
+        o.p[c] = grad_src->x[c];
+        o.p[3 + c] = grad_src->v[c];
+        o.p[6 + c] = grad_src->a[c];
+    }
+    o.p[9] = grad_m;
+    H6_TRY(ctx, launch_eval_vjp(ctx, 2, src_from_pred(src, m), g, (int)n, o, 1u << 9),
+           "evaluate vjp");
+    return H6_OK;
+}
+
+int h6_correct_shared_vjp(h6_ctx ctx, h6_state *cot, int64_t n, const h6_force *cot_force,
+                          double dt) {
+    if (!ctx) return H6_EINVAL;
+    if (!state_ok(cot, false) || !force_ok(cot_force)) return fail_arg(ctx, "null array");
+    if (int rc = check_n(ctx, n)) return rc;
+    if (!std::isfinite(dt) || dt <= 0.0) return fail_arg(ctx, "dt must be positive");
+    H6_TRY(ctx, launch_correct_shared_vjp(ctx, cot, (int)n, cot_force, dt), "correct vjp");
+    return H6_OK;
+}
+
+int h6_predict_dt_vjp(h6_ctx ctx, h6_state *cot, int64_t n, const h6_pred *cot_pred, double dt) {
+    if (!ctx) return H6_EINVAL;
+    if (!state_ok(cot, false) || !pred_ok(cot_pred)) return fail_arg(ctx, "null array");
+    if (int rc = check_n(ctx, n)) return rc;
+    if (!std::isfinite(dt)) return fail_arg(ctx, "dt not finite");
+    H6_TRY(ctx, launch_predict_dt_vjp(ctx, cot, (int)n, cot_pred, dt), "predict vjp");
+    return H6_OK;
+}
+
+int h6_init_forces_vjp(h6_ctx ctx, const h6_state *st, int64_t n, h6_state *cot) {
+    if (!ctx) return H6_EINVAL;
+    if (!state_ok(st, false) || !state_ok(cot, false)) return fail_arg(ctx, "null array");
+    if (int rc = check_n(ctx, n)) return rc;
+    // pass 2, (s, c) from (x, v, a, j, m): cotangents (sbar, cbar); adds
+    // into xbar, vbar, abar, jbar, mbar
+    SrcPtrs s2;
+    for (int c = 0; c < 3; ++c) {
+        s2.x[c] = st->x[c];
+        s2.v[c] = st->v[c];
+        s2.a[c] = st->a[c];
+        s2.j[c] = st->j[c];
+    }
+    s2.m = st->m;
+    const double *g2[6];
+    for (int c = 0; c < 3; ++c) {
+        g2[c] = cot->s[c];
+        g2[3 + c] = cot->c[c];
+    }
+    OutPtrs o;
+    for (int c = 0; c < kMaxOut; ++c) o.p[c] = nullptr;
+    for (int c = 0; c < 3; ++c) {
+        o.p[c] = cot->x[c];
+        o.p[3 + c] = cot->v[c];
+        o.p[6 + c] = cot->a[c];
+        o.p[9 + c] = cot->j[c];
+    }
+    o.p[12] = cot->m;
+    H6_TRY(ctx, launch_eval_vjp(ctx, 3, s2, g2, (int)n, o, 0x1fffu), "init vjp pass 2");
+    // pass 1, (a, j) from (x, v, m): cotangents (abar, jbar) now complete
+    SrcPtrs s1 = s2;
+    for (int c = 0; c < 3; ++c) {
+        s1.a[c] = nullptr;
+        s1.j[c] = nullptr;
+    }
+    const double *g1[6];
+    for (int c = 0; c < 3; ++c) {
+        g1[c] = cot->a[c];
+        g1[3 + c] = cot->j[c];
+    }
+    OutPtrs o1;
+    for (int c = 0; c < kMaxOut; ++c) o1.p[c] = nullptr;
+    for (int c = 0; c < 3; ++c) {
+        o1.p[c] = cot->x[c];
+        o1.p[3 + c] = cot->v[c];
+    }
+    o1.p[6] = cot->m;
+    H6_TRY(ctx, launch_eval_vjp(ctx, 1, s1, g1, (int)n, o1, 0x7fu), "init vjp pass 1");
     return H6_OK;
 }
 

@@ -21,6 +21,10 @@
 //     pair, so rounding grows with the number of tiles, not sources;
 //   * no floating-point atomics: results are bitwise reproducible for a
 //     given launch shape.
+#include <algorithm>
+#include <climits>
+
+#include "device_math.h"
 #include "h6_internal.h"
 
 namespace h6 {
@@ -49,27 +53,6 @@ struct Traits<3> {
     static constexpr int NACC = 6;
     static constexpr int OUT0 = 6;
 };
-
-// 1/sqrt(r2): hardware estimate plus one Newton step of third order,
-//   e = 1 - r2 y^2,  y <- y (1 + e/2 + 3 e^2/8),
-// which takes a relative error d to about (5/2) d^3.
-__device__ __forceinline__ double rsqrt_f64(double r2) {
-    double y = __builtin_amdgcn_rsq(r2);
-    double t = r2 * y;
-    double e = fma(-t, y, 1.0);
-    double p = fma(e, 0.375, 0.5);
-    double ye = y * e;
-    return fma(ye, p, y);
-}
-
-// hi + lo += x without loss (Knuth's TwoSum on hi, error into lo).
-__device__ __forceinline__ void two_sum_into(double &hi, double &lo, double x) {
-    double s = hi + x;
-    double bp = s - hi;
-    double err = (hi - (s - bp)) + (x - bp);
-    hi = s;
-    lo += err;
-}
 
 // Pair terms of order 2 (a, j, s) accumulated into acc[0..8], from the
 // differences source - target r, v, a and the source mass. With
@@ -279,21 +262,11 @@ __attribute__((amdgpu_waves_per_eu(IPL == 1 ? 4 : 2))) void k_eval_f64(SrcPtrs s
     }
 }
 
-// Compensated sum of (s1, c1) and (s2, c2): TwoSum of the leading parts,
-// compensations added.
-__device__ __forceinline__ void comp_merge(double &s, double &c, double s2, double c2) {
-    const double t = s + s2;
-    const double bp = t - s;
-    const double err = (s - (t - bp)) + (s2 - bp);
-    s = t;
-    c += err + c2;
-}
-
 // Slice reduction, few slices: one thread per (component, target), a
 // Neumaier sum over the slices with all loads issued up front.
 __global__ __launch_bounds__(256) void k_reduce_slices(const double *__restrict__ partial,
                                                        int64_t ld, int n_split, int ncomp, int out0,
-                                                       int n_act, OutPtrs out) {
+                                                       int n_act, OutPtrs out, unsigned acc_mask) {
     const int64_t total = (int64_t)ncomp * n_act;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
@@ -312,7 +285,8 @@ __global__ __launch_bounds__(256) void k_reduce_slices(const double *__restrict_
                 s = t;
             }
         }
-        out.p[out0 + c][k] = s + comp;
+        double *dst = &out.p[out0 + c][k];
+        *dst = ((acc_mask >> c) & 1u) ? *dst + (s + comp) : s + comp;
     }
 }
 
@@ -321,7 +295,8 @@ __global__ __launch_bounds__(256) void k_reduce_slices(const double *__restrict_
 // merges combines the lanes, so the result does not depend on timing.
 __global__ __launch_bounds__(256) void k_reduce_slices_wave(const double *__restrict__ partial,
                                                             int64_t ld, int n_split, int ncomp,
-                                                            int out0, int n_act, OutPtrs out) {
+                                                            int out0, int n_act, OutPtrs out,
+                                                            unsigned acc_mask) {
     const int lane = threadIdx.x & 63;
     const int64_t total = (int64_t)ncomp * n_act;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
@@ -336,18 +311,11 @@ __global__ __launch_bounds__(256) void k_reduce_slices_wave(const double *__rest
             comp += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
             s = t;
         }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            const double s2 = __shfl_xor(s, off, 64);
-            const double c2 = __shfl_xor(comp, off, 64);
-            // both partners form the same pair in the same order
-            double a = (lane & off) ? s2 : s, ac = (lane & off) ? c2 : comp;
-            const double b = (lane & off) ? s : s2, bc = (lane & off) ? comp : c2;
-            comp_merge(a, ac, b, bc);
-            s = a;
-            comp = ac;
+        wave_comp_sum(s, comp);
+        if (lane == 0) {
+            double *dst = &out.p[out0 + c][k];
+            *dst = ((acc_mask >> c) & 1u) ? *dst + (s + comp) : s + comp;
         }
-        if (lane == 0) out.p[out0 + c][k] = s + comp;
     }
 }
 
@@ -424,16 +392,7 @@ __global__ __launch_bounds__(64) void k_eval_small(SrcPtrs src, const int32_t *_
         for (int q = 0; q < 9; ++q) {
             two_sum_into(hi[t][q], lo[t][q], acc[t][q]);
             double sv = hi[t][q], cv = lo[t][q];
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double s2 = __shfl_xor(sv, off, 64);
-                const double c2 = __shfl_xor(cv, off, 64);
-                double a = (lane & off) ? s2 : sv, ac = (lane & off) ? c2 : cv;
-                const double b = (lane & off) ? sv : s2, bc = (lane & off) ? cv : c2;
-                comp_merge(a, ac, b, bc);
-                sv = a;
-                cv = ac;
-            }
+            wave_comp_sum(sv, cv);
             const int k = wave * TPW + t;
             if (lane == 0 && k < n_act) out.p[q][soff + k] = sv + cv;
         }
@@ -508,6 +467,37 @@ constexpr int kSmallMinSlice = 256;
 
 }  // namespace
 
+// Number of source slices for a target-parallel kernel of `block` threads
+// per workgroup whose register footprint allows `waves_per_simd` waves on a
+// SIMD. A launch of W workgroups runs in rounds of the resident ones (CUs x
+// waves per SIMD x 4 SIMDs / waves per workgroup), so it takes about
+// ceil(W / resident) x (slice length + per-workgroup overhead); pick the
+// slice count minimising that (fewest slices on ties, to keep the
+// reduction small), with at least four tiles per slice.
+int balanced_split(h6_ctx ctx, int waves_per_simd, int block, int n, int blocks_i) {
+    const int wg_per_cu = std::max(1, waves_per_simd * 4 / (block / 64));
+    const int64_t resident = (int64_t)ctx->n_cu * wg_per_cu;
+    const int max_split = std::max(1, ceil_div(n, 4 * block));
+    const int64_t overhead = 2 * block;  // target loads, partial stores, reduction share
+    int best = 1;
+    int64_t best_cost = INT64_MAX;
+    int last_eff = -1;
+    for (int sp = 1; sp <= max_split; ++sp) {
+        const int slice = ceil_div(ceil_div(n, sp), block) * block;
+        const int eff = ceil_div(n, slice);
+        if (eff == last_eff) continue;
+        last_eff = eff;
+        const int64_t w = (int64_t)blocks_i * eff;
+        const int64_t rounds = (w + resident - 1) / resident;
+        const int64_t cost = rounds * (slice + overhead);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = eff;
+        }
+    }
+    return best;
+}
+
 EvalConfig choose_eval_config(h6_ctx ctx, int order, int precision, int n, int n_act) {
     (void)precision;
     EvalConfig cfg;
@@ -542,11 +532,11 @@ EvalConfig choose_eval_config(h6_ctx ctx, int order, int precision, int n, int n
     if (ctx->cfg_split && order == 2) {
         split = ctx->cfg_split;
     } else {
-        // about kTargetWaves waves in flight on 256 CUs
-        split = ceil_div((int64_t)kTargetWaves * 64, (int64_t)blocks_i * cfg.block);
-        // each slice holds at least four tiles of sources
-        const int max_split = ceil_div(n, 4 * cfg.block);
-        if (split > max_split) split = max_split;
+        // measured footprints on gfx950: order 2 with one target per lane
+        // <= 128 VGPRs (4 waves per SIMD), two per lane <= 256 (2 waves);
+        // start-up passes <= 128
+        const int waves_per_simd = (order == 2 && cfg.ipl == 2) ? 2 : 4;
+        split = balanced_split(ctx, waves_per_simd, cfg.block, n, blocks_i);
     }
     const int max_by_tiles = ceil_div(n, cfg.block);
     if (split > max_by_tiles) split = max_by_tiles;
@@ -580,7 +570,7 @@ hipError_t launch_eval(h6_ctx ctx, int order, int precision, const SrcPtrs &src,
     if (cfg.n_split == 1) {
         dst = out;
     } else {
-        for (int c = 0; c < 12; ++c) dst.p[c] = nullptr;
+        for (int c = 0; c < kMaxOut; ++c) dst.p[c] = nullptr;
         for (int c = 0; c < ncomp; ++c) dst.p[out0 + c] = ctx->partial + (int64_t)c * n_act;
         slice_stride = (int64_t)ncomp * n_act;
     }
@@ -590,7 +580,11 @@ hipError_t launch_eval(h6_ctx ctx, int order, int precision, const SrcPtrs &src,
         if (pe != hipSuccess) return pe;
     }
     hipError_t e;
-    if (cfg.kind == 1) {
+    if (order == 2 && precision == H6_MIXED) {
+        dim3 g = cfg.kind == 1 ? dim3(ceil_div(n_act, cfg.ipl), cfg.n_split) : grid;
+        e = dispatch_mixed(cfg, skipself, g, ctx->stream, src, active, n, n_act, ctx->eps2,
+                           slice_len, dst, slice_stride);
+    } else if (cfg.kind == 1) {
         dim3 g(ceil_div(n_act, cfg.ipl), cfg.n_split);
         e = dispatch_small(cfg.ipl, skipself, g, ctx->stream, src, active, n, n_act, ctx->eps2,
                            slice_len, dst, slice_stride);
@@ -606,17 +600,22 @@ hipError_t launch_eval(h6_ctx ctx, int order, int precision, const SrcPtrs &src,
     if (e == hipSuccess && ctx->prof)
         e = prof_end(ctx, ev0, ev1, order, cfg, precision, n_act, (double)n_act * (double)n);
     if (e != hipSuccess || cfg.n_split == 1) return e;
+    return launch_reduce(ctx, cfg.n_split, ncomp, out0, n_act, out, 0u);
+}
+
+hipError_t launch_reduce(h6_ctx ctx, int n_split, int ncomp, int out0, int n_act,
+                         const OutPtrs &out, unsigned acc_mask) {
     const int64_t total = (int64_t)ncomp * n_act;
-    if (cfg.n_split >= kWaveReduceMinSplit) {
+    if (n_split >= kWaveReduceMinSplit) {
         int rb = ceil_div(total, 4);
         if (rb > 8192) rb = 8192;
         hipLaunchKernelGGL(k_reduce_slices_wave, dim3(rb), dim3(256), 0, ctx->stream, ctx->partial,
-                           (int64_t)n_act, cfg.n_split, ncomp, out0, n_act, out);
+                           (int64_t)n_act, n_split, ncomp, out0, n_act, out, acc_mask);
     } else {
         int rb = ceil_div(total, 256);
         if (rb > 4096) rb = 4096;
         hipLaunchKernelGGL(k_reduce_slices, dim3(rb), dim3(256), 0, ctx->stream, ctx->partial,
-                           (int64_t)n_act, cfg.n_split, ncomp, out0, n_act, out);
+                           (int64_t)n_act, n_split, ncomp, out0, n_act, out, acc_mask);
     }
     return hipGetLastError();
 }

@@ -27,8 +27,9 @@ struct SrcPtrs {
 
 // Output arrays by component: component c of target k of slice s lives at
 // p[c][s * slice_stride + k].
+constexpr int kMaxOut = 16;
 struct OutPtrs {
-    double *p[12];
+    double *p[kMaxOut];
 };
 
 struct EvalConfig {
@@ -45,6 +46,7 @@ struct h6_ctx_s {
     double eps = 0.0, eps2 = 0.0;
     hipStream_t stream = nullptr;
     int device = 0;
+    int n_cu = 256;  // compute units of the device
     int cfg_block = 0, cfg_ipl = 0, cfg_split = 0;  // 0: automatic
     int cfg_small = -1;                             // < 0: built-in threshold
     // scratch (device)
@@ -78,6 +80,17 @@ hipError_t launch_eval(h6_ctx ctx, int order, int precision, const SrcPtrs &src,
                        const int32_t *active, int n_act, const OutPtrs &out,
                        EvalConfig *used);
 EvalConfig choose_eval_config(h6_ctx ctx, int order, int precision, int n, int n_act);
+// Compensated sum over n_split slices of ncomp partial arrays of n_act
+// targets (ctx->partial, [slice][comp][target]) into out.p[out0 + comp];
+// bit c of acc_mask adds to the existing value instead of overwriting.
+hipError_t launch_reduce(h6_ctx ctx, int n_split, int ncomp, int out0, int n_act,
+                         const OutPtrs &out, unsigned acc_mask);
+int balanced_split(h6_ctx ctx, int waves_per_simd, int block, int n, int blocks_i);
+// Mixed-precision order-2 kernels (eval_mixed.hip), launched with the shape
+// chosen for the FP64 kernels.
+hipError_t dispatch_mixed(const EvalConfig &cfg, bool skipself, dim3 grid, hipStream_t st,
+                          const SrcPtrs &src, const int32_t *active, int n, int n_act, double eps2,
+                          int slice_len, const OutPtrs &out, int64_t slice_stride);
 
 hipError_t launch_predict(h6_ctx ctx, const h6_state *st, int n, int64_t t_tick, double dt,
                           bool shared, const h6_pred *out);
@@ -88,6 +101,13 @@ hipError_t launch_initial_steps(h6_ctx ctx, h6_state *st, int n, double eta_s, i
                                 int lev_max);
 hipError_t launch_next_block(h6_ctx ctx, const h6_state *st, int n, int32_t *active);
 hipError_t launch_energy(h6_ctx ctx, const h6_state *st, int n);
+
+// Adjoint kernels (adjoint.hip).
+hipError_t launch_eval_vjp(h6_ctx ctx, int order, const SrcPtrs &src, const double *const *cot,
+                           int n, const OutPtrs &out, unsigned acc_mask);
+hipError_t launch_correct_shared_vjp(h6_ctx ctx, h6_state *cot, int n, const h6_force *cf,
+                                     double dt);
+hipError_t launch_predict_dt_vjp(h6_ctx ctx, h6_state *cot, int n, const h6_pred *cp, double dt);
 
 int sched_blocks_for(int64_t n);
 // Measurement hook helpers (api.hip).

@@ -5,6 +5,7 @@
 // All of these are bandwidth- or latency-bound elementwise passes over
 // structure-of-arrays FP64 data: one particle per lane, coalesced loads
 // and stores, no LDS except for block-level reductions.
+#include "device_math.h"
 #include "h6_internal.h"
 
 namespace h6 {
@@ -163,12 +164,14 @@ __global__ __launch_bounds__(256) void k_initial_steps(h6_state st, int n, doubl
 }
 
 // ---------------------------------------------------------------- scheduler
-// Three passes over fixed chunks of kSchedChunk particles per workgroup:
-//   1. chunk minima of t + dt; the last workgroup to finish reduces them to
-//      t_next;
-//   2. chunk counts of particles due at t_next; the last workgroup scans
-//      them into chunk offsets and the total n_act;
-//   3. each chunk writes its due particles, in index order, at its offset.
+// Two passes over fixed chunks of kSchedChunk particles per workgroup:
+//   1. each chunk finds its minimum due time t + dt and how many of its
+//      particles are due then; the last workgroup to finish takes the
+//      global minimum t_next, gives every chunk whose minimum equals t_next
+//      an offset (exclusive scan of their counts, in chunk order) and
+//      publishes t_next and n_act;
+//   2. each such chunk writes its due particles, in index order, at its
+//      offset.
 constexpr int kSchedThreads = 256;
 constexpr int kSchedChunk = kSchedThreads * 16;
 
@@ -219,10 +222,26 @@ __device__ __forceinline__ int64_t block_min_i64(int64_t v) {
     return r;
 }
 
-__global__ __launch_bounds__(kSchedThreads) void k_sched_min(const int64_t *__restrict__ t,
-                                                             const int64_t *__restrict__ dt, int n,
-                                                             int64_t *blockmin, unsigned *counter,
-                                                             int64_t *t_next) {
+__device__ __forceinline__ int block_sum_i32(int v) {
+    __shared__ int wsum[kSchedThreads / 64];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int r = 0;
+#pragma unroll
+    for (int q = 0; q < kSchedThreads / 64; ++q) r += wsum[q];
+    __syncthreads();
+    return r;
+}
+
+// out[0] = t_next, out[1] = n_act (the 16 bytes the host reads back)
+__global__ __launch_bounds__(kSchedThreads) void k_sched_select(const int64_t *__restrict__ t,
+                                                                const int64_t *__restrict__ dt,
+                                                                int n, int64_t *chunk_min,
+                                                                int32_t *chunk_cnt,
+                                                                int32_t *chunk_off,
+                                                                unsigned *counter, int64_t *out) {
     const int base = blockIdx.x * kSchedChunk;
     const int end = min(n, base + kSchedChunk);
     int64_t v = INT64_MAX;
@@ -230,66 +249,47 @@ __global__ __launch_bounds__(kSchedThreads) void k_sched_min(const int64_t *__re
         const int64_t due = t[i] + dt[i];
         v = due < v ? due : v;
     }
-    v = block_min_i64(v);
-    if (threadIdx.x == 0) blockmin[blockIdx.x] = v;
+    const int64_t cmin = block_min_i64(v);
+    int cnt = 0;
+    for (int i = base + threadIdx.x; i < end; i += kSchedThreads) cnt += (t[i] + dt[i] == cmin);
+    cnt = block_sum_i32(cnt);
+    if (threadIdx.x == 0) {
+        chunk_min[blockIdx.x] = cmin;
+        chunk_cnt[blockIdx.x] = cnt;
+    }
     if (!last_workgroup(counter, gridDim.x)) return;
     int64_t r = INT64_MAX;
     for (int b = threadIdx.x; b < (int)gridDim.x; b += kSchedThreads) {
-        const int64_t x = load_agent(&blockmin[b]);
+        const int64_t x = load_agent(&chunk_min[b]);
         r = x < r ? x : r;
     }
     r = block_min_i64(r);
-    if (threadIdx.x == 0) *t_next = r;
-}
-
-__global__ __launch_bounds__(kSchedThreads) void k_sched_count(const int64_t *__restrict__ t,
-                                                               const int64_t *__restrict__ dt,
-                                                               int n, const int64_t *t_next,
-                                                               int32_t *blockcnt, int32_t *blockoff,
-                                                               unsigned *counter, int32_t *n_act,
-                                                               int64_t *t_next_host_copy) {
-    const int64_t tn = *t_next;
-    const int base = blockIdx.x * kSchedChunk;
-    const int end = min(n, base + kSchedChunk);
-    int cnt = 0;
-    for (int i = base + threadIdx.x; i < end; i += kSchedThreads) cnt += (t[i] + dt[i] == tn);
-    // block sum
-    __shared__ int wsum[kSchedThreads / 64];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = cnt;
-    __syncthreads();
     if (threadIdx.x == 0) {
-        int s = 0;
-#pragma unroll
-        for (int q = 0; q < kSchedThreads / 64; ++q) s += wsum[q];
-        blockcnt[blockIdx.x] = s;
-    }
-    if (!last_workgroup(counter, gridDim.x)) return;
-    if (threadIdx.x == 0) {
-        // exclusive scan over the (few hundred at most) chunk counts
+        // exclusive scan over the (few hundred at most) chunks that hold t_next
         int run = 0;
         for (int b = 0; b < (int)gridDim.x; ++b) {
-            const int c = load_agent(&blockcnt[b]);
-            blockoff[b] = run;
-            run += c;
+            const bool has = load_agent(&chunk_min[b]) == r;
+            chunk_off[b] = has ? run : -1;
+            run += has ? load_agent(&chunk_cnt[b]) : 0;
         }
-        *n_act = run;
-        *t_next_host_copy = tn;
+        out[0] = r;
+        out[1] = run;
     }
 }
 
 __global__ __launch_bounds__(kSchedThreads) void k_sched_compact(const int64_t *__restrict__ t,
                                                                  const int64_t *__restrict__ dt,
-                                                                 int n, const int64_t *t_next,
-                                                                 const int32_t *blockoff,
+                                                                 int n, const int64_t *sel,
+                                                                 const int32_t *chunk_off,
                                                                  int32_t *active) {
     __shared__ int wcnt[kSchedThreads / 64];
-    const int64_t tn = *t_next;
+    const int off0 = chunk_off[blockIdx.x];
+    if (off0 < 0) return;  // no particle of this chunk is due
+    const int64_t tn = sel[0];
     const int base = blockIdx.x * kSchedChunk;
     const int end = min(n, base + kSchedChunk);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int run = blockoff[blockIdx.x];
+    int run = off0;
     for (int r = base; r < end; r += kSchedThreads) {
         const int i = r + threadIdx.x;
         const bool due = i < end && (t[i] + dt[i] == tn);
@@ -311,15 +311,6 @@ __global__ __launch_bounds__(kSchedThreads) void k_sched_compact(const int64_t *
 
 // ---------------------------------------------------------------- energy
 constexpr int kEnergyThreads = 256;
-
-__device__ __forceinline__ double rsqrt_f64(double r2) {
-    double y = __builtin_amdgcn_rsq(r2);
-    double t = r2 * y;
-    double e = fma(-t, y, 1.0);
-    double p = fma(e, 0.375, 0.5);
-    double ye = y * e;
-    return fma(ye, p, y);
-}
 
 __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
     s = a + b;
@@ -443,23 +434,19 @@ hipError_t launch_initial_steps(h6_ctx ctx, h6_state *st, int n, double eta_s, i
     return hipGetLastError();
 }
 
-// Scratch layout (ctx->sched64): [0] t_next, [1] t_next copy for the host,
-// [2..] chunk minima. ctx->sched32: [0] n_act, [1..nb] counts,
-// [1+nb..2nb] offsets. counters[0..1]: min and count hand-offs.
+// Scratch layout: ctx->sched64[0..1] = {t_next, n_act} (read back by the
+// host), ctx->sched64[2..] chunk minima; ctx->sched32[0..nb) chunk counts,
+// [nb..2nb) chunk offsets; counters[0] is the hand-off counter.
 hipError_t launch_next_block(h6_ctx ctx, const h6_state *st, int n, int32_t *active) {
     const int nb = sched_blocks_for(n);
-    int64_t *t_next = ctx->sched64;
-    int64_t *t_copy = ctx->sched64 + 1;
-    int64_t *bmin = ctx->sched64 + 2;
-    int32_t *n_act = ctx->sched32;
-    int32_t *bcnt = ctx->sched32 + 1;
-    int32_t *boff = ctx->sched32 + 1 + nb;
-    hipLaunchKernelGGL(k_sched_min, dim3(nb), dim3(kSchedThreads), 0, ctx->stream, st->t, st->dt, n,
-                       bmin, ctx->counters, t_next);
-    hipLaunchKernelGGL(k_sched_count, dim3(nb), dim3(kSchedThreads), 0, ctx->stream, st->t, st->dt,
-                       n, (const int64_t *)t_next, bcnt, boff, ctx->counters + 1, n_act, t_copy);
+    int64_t *sel = ctx->sched64;
+    int64_t *cmin = ctx->sched64 + 2;
+    int32_t *ccnt = ctx->sched32;
+    int32_t *coff = ctx->sched32 + nb;
+    hipLaunchKernelGGL(k_sched_select, dim3(nb), dim3(kSchedThreads), 0, ctx->stream, st->t, st->dt,
+                       n, cmin, ccnt, coff, ctx->counters, sel);
     hipLaunchKernelGGL(k_sched_compact, dim3(nb), dim3(kSchedThreads), 0, ctx->stream, st->t,
-                       st->dt, n, (const int64_t *)t_next, (const int32_t *)boff, active);
+                       st->dt, n, (const int64_t *)sel, (const int32_t *)coff, active);
     return hipGetLastError();
 }
 

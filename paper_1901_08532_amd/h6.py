@@ -98,6 +98,14 @@ _SIGS = {
                                   C.POINTER(h6_force), C.c_double, C.c_int64, C.c_int]),
     "h6_energy": (C.c_int, [C.c_void_p, C.POINTER(h6_state), C.c_int64, C.POINTER(C.c_double)]),
     "h6_check_status": (C.c_int, [C.c_void_p]),
+    "h6_evaluate_vjp": (C.c_int, [C.c_void_p, C.POINTER(h6_pred), C.c_void_p, C.c_int64,
+                                  C.POINTER(h6_force), C.POINTER(h6_pred), C.c_void_p]),
+    "h6_correct_shared_vjp": (C.c_int, [C.c_void_p, C.POINTER(h6_state), C.c_int64,
+                                        C.POINTER(h6_force), C.c_double]),
+    "h6_predict_dt_vjp": (C.c_int, [C.c_void_p, C.POINTER(h6_state), C.c_int64,
+                                    C.POINTER(h6_pred), C.c_double]),
+    "h6_init_forces_vjp": (C.c_int, [C.c_void_p, C.POINTER(h6_state), C.c_int64,
+                                     C.POINTER(h6_state)]),
     "h6_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "h6_profile_read": (C.c_int, [C.c_void_p, C.POINTER(h6_eval_timing), C.c_int,
                                   C.POINTER(C.c_int)]),
@@ -288,6 +296,29 @@ class Context:
         out = (C.c_double * 5)()
         self._check(lib().h6_energy(self._h, C.byref(st), S.shape[1], out), "h6_energy")
         return float(out[0]), float(out[1]), [float(out[2]), float(out[3]), float(out[4])]
+
+    # ---- adjoint -------------------------------------------------------
+    def h6_evaluate_vjp(self, P, m, CF, GP, gm):
+        pr, cf, gp = make_pred(P), make_force(CF), make_pred(GP)
+        return self._check(lib().h6_evaluate_vjp(self._h, C.byref(pr), _ptr(m), P.shape[1],
+                                                 C.byref(cf), C.byref(gp), _ptr(gm)),
+                           "h6_evaluate_vjp")
+
+    def h6_correct_shared_vjp(self, CS, gm, CF, dt):
+        cs, cf = make_state(CS, gm, None), make_force(CF)
+        return self._check(lib().h6_correct_shared_vjp(self._h, C.byref(cs), CS.shape[1],
+                                                       C.byref(cf), float(dt)),
+                           "h6_correct_shared_vjp")
+
+    def h6_predict_dt_vjp(self, CS, gm, CP, dt):
+        cs, cp = make_state(CS, gm, None), make_pred(CP)
+        return self._check(lib().h6_predict_dt_vjp(self._h, C.byref(cs), CS.shape[1], C.byref(cp),
+                                                   float(dt)), "h6_predict_dt_vjp")
+
+    def h6_init_forces_vjp(self, S, m, CS, gm):
+        st, cs = make_state(S, m, None), make_state(CS, gm, None)
+        return self._check(lib().h6_init_forces_vjp(self._h, C.byref(st), S.shape[1], C.byref(cs)),
+                           "h6_init_forces_vjp")
 
     def h6_check_status(self):
         return lib().h6_check_status(self._h)

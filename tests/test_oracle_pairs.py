@@ -133,3 +133,17 @@ def test_kepler_energy_and_angular_momentum():
         ek, ep, L = oracle.energy(x, v, np.array([0.7, 0.3]), 0.0)
         assert abs(ek + ep - k.energy()) < 1e-14
         assert abs(L[2] - k.ang_mom()) < 1e-14 and abs(L[0]) < 1e-16 and abs(L[1]) < 1e-16
+
+
+def test_absolute_sums_bound_the_sums():
+    x, v, m = ics.plummer(300, 12)
+    a, _, _, _ = oracle.forces(x, v, m, 1e-6, order=1)
+    F = oracle.forces(x, v, m, 1e-6, a=a, order=2)
+    Fa = oracle.forces(x, v, m, 1e-6, a=a, order=2, absolute=True)
+    for f, fa in zip(F[:3], Fa[:3]):
+        assert np.all(fa >= np.abs(f) * (1 - 1e-14))
+    # a single source: the absolute sum is the absolute value
+    Fs = oracle.forces(x[:2], v[:2], m[:2], 1e-6, a=a[:2], order=2)
+    Fsa = oracle.forces(x[:2], v[:2], m[:2], 1e-6, a=a[:2], order=2, absolute=True)
+    for f, fa in zip(Fs[:3], Fsa[:3]):
+        assert np.array_equal(np.abs(f), fa)
