@@ -74,6 +74,11 @@ def main():
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--workload", choices=("plummer", "plummer-imf", "two-clusters"),
+                    default="plummer",
+                    help="equal-mass Plummer sphere; Plummer with dN/dm ~ m^-2.35 masses "
+                         "(mass seed 10*seed+seed); two Plummer spheres of n/2 on a head-on "
+                         "approach (seeds seed, 10*seed+seed)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -104,8 +109,15 @@ def main():
     prec = h6.H6_FP64 if args.precision == "fp64" else h6.H6_MIXED
     sync_ticks = 1 << (h6.TICK_BITS - lev_min)
 
-    _log("inputs: Plummer N=%d seed=%d" % (n, args.seed))
-    x, v, m = ics.plummer(n, args.seed)
+    seed2 = 10 * args.seed + args.seed
+    _log("inputs: %s N=%d seed=%d" % (args.workload, n, args.seed))
+    if args.workload == "plummer":
+        x, v, m = ics.plummer(n, args.seed)
+    elif args.workload == "plummer-imf":
+        x, v, _ = ics.plummer(n, args.seed)
+        m = ics.salpeter_masses(n, seed2)
+    else:
+        x, v, m = ics.two_clusters(n // 2, args.seed, seed2)
     sysg = h6.System(x, v, m, eps)
     sysg.startup(eta_s=0.1, lev_min=lev_min, lev_max=lev_max)
     rc = sysg.ctx.h6_check_status()
@@ -242,7 +254,8 @@ def main():
         "dtype": "f64" if prec == h6.H6_FP64 else "f64+f32",
         "data": "synthetic",
         "config": {
-            "workload": "plummer_n%d_eps1e-4_blocksteps_eta0.4_dtmax1/16_%gtu" % (n, args.steps / 16),
+            "workload": "%s_n%d_eps1e-4_blocksteps_eta0.4_dtmax1/16_%gtu_%s" % (
+                args.workload.replace("-", "_"), n, args.steps / 16, args.precision),
             "n": n, "eps": eps, "eta": eta, "dt_max": 2.0 ** -lev_min, "lev_max": lev_max,
             "time_units": args.steps / 16.0, "precision": args.precision, "seed": args.seed,
             "flops_per_interaction": FLOPS_PER_INTERACTION,

@@ -121,7 +121,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise H6Error(H6_ESTATE, "load", "%s not built (run __graft_entry__.build())" % LIB_PATH)
+            raise H6Error(H6_ESTATE, "load", "%s not built (run python -m paper_1901_08532_amd.build)" % LIB_PATH)
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
