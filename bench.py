@@ -40,21 +40,41 @@ METRIC = "a/j/s pair interactions/s, % of vector FP peak, at stated rel. error v
 FLOPS_PER_INTERACTION = 78  # FMA 2, rsqrt 1, potential excluded
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eval_f64_hbm_traffic.txt")
-EVAL_SOURCE = os.path.join(ROOT, "paper_1901_08532_amd", "csrc", "eval.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eval_hbm_traffic.txt")
+CSRC = os.path.join(ROOT, "paper_1901_08532_amd", "csrc")
+# the evaluation kernels' sources: the traffic record is void once any changes
+EVAL_SOURCES = ("eval_body.h", "eval_mixed_body.h", "device_math.h", "blockloop.hip", "eval.hip",
+                "eval_mixed.hip")
 
 
 def _log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def _traffic_per_launch(block, ipl):
-    """HBM bytes per launch of the given instantiation from the committed
-    rocprofv3 counter summary, or None when the kernel source changed since
-    the counters were taken."""
+def _kernel_name(rec, mixed):
+    """Kernel symbol (as rocprofv3 shows it) of an evaluation timing record."""
+    if rec["kind"] == 2:
+        return "k_bl_eval<%s, false>" % ("true" if mixed else "false")
+    if rec["kind"] == 1:
+        return "k_eval_small%s<%d, false>" % ("_mixed" if mixed else "", rec["ipl"])
+    if mixed:
+        return "k_eval_mixed<%d, %d, false>" % (rec["block"], rec["ipl"])
+    return "k_eval_f64<2, %d, %d, false>" % (rec["block"], rec["ipl"])
+
+
+def _traffic_tag(rec, mixed):
+    if rec["kind"] == 2:
+        return "bl_eval_%s" % ("mixed" if mixed else "fp64")
+    return "b%d_i%d" % (rec["block"], rec["ipl"])
+
+
+def _traffic_per_launch(tag):
+    """HBM bytes per launch of the given kernel from the committed rocprofv3
+    counter summary, or None when the evaluation sources changed since the
+    counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
-    want = hashlib.sha256(open(EVAL_SOURCE, "rb").read()).hexdigest()
+    want = _eval_sources_sha256()
     fields = {}
     for line in open(TRAFFIC_FILE):
         if "=" in line and not line.lstrip().startswith("#"):
@@ -62,8 +82,15 @@ def _traffic_per_launch(block, ipl):
             fields[k.strip()] = v.strip()
     if fields.get("eval_source_sha256") != want:
         return None
-    key = "hbm_bytes_per_launch_b%d_i%d" % (block, ipl)
+    key = "hbm_bytes_per_launch_" + tag
     return float(fields[key]) if key in fields else None
+
+
+def _eval_sources_sha256():
+    h = hashlib.sha256()
+    for f in EVAL_SOURCES:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()
 
 
 def main():
@@ -82,6 +109,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--host-loop", action="store_true",
+                    help="one host round trip per block instead of the device-resident loop")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -128,7 +157,8 @@ def main():
     E0 = e_start[0] + e_start[1]
 
     def one_step(k):
-        rc, stats = sysg.run_blocks((k + 1) * sync_ticks, eta, lev_min, lev_max, prec, check=False)
+        rc, stats = sysg.run_blocks((k + 1) * sync_ticks, eta, lev_min, lev_max, prec, check=False,
+                                    host_loop=args.host_loop)
         if rc != h6.H6_OK:
             raise h6.H6Error(rc, "h6_run_blocks", h6.lib().h6_last_error(sysg.ctx.handle).decode())
         e = sysg.energy()
@@ -160,7 +190,8 @@ def main():
     value = inter / wall if wall > 0 else 0.0
     _log("timed %d steps: %d blocks, %.3e interactions, %.3f s" % (args.steps, blocks, inter, wall))
 
-    # per instantiation (summed over active-set bins) and per active-set bin
+    # per instantiation (summed over active-set bins) and per active-set bin;
+    # bin -1 holds the evaluation launches of empty blocks (device loop)
     evals = [p for p in prof if p["order"] == 2]
     inst = {}
     bins = {}
@@ -177,6 +208,8 @@ def main():
     eval_ms = sum(p["kernel_ms"] for p in evals)
     by_active = []
     for b in sorted(bins):
+        if b < 0:
+            continue
         d = bins[b]
         rate = d["interactions"] / (d["kernel_ms"] * 1e-3)
         by_active.append({"n_act_from": 1 << b, "n_act_below": 1 << (b + 1), "launches": d["launches"],
@@ -184,7 +217,7 @@ def main():
                           "eval_interactions_per_s": rate,
                           "eval_pct_fp64_peak": 100.0 * rate * FLOPS_PER_INTERACTION / (FP64_PEAK_TFLOPS * 1e12)})
     achieved = FLOPS_PER_INTERACTION * dom["interactions"] / (dom["kernel_ms"] * 1e-3) / 1e12
-    traffic = _traffic_per_launch(dom["block"], dom["ipl"])
+    traffic = _traffic_per_launch(_traffic_tag(dom, prec == h6.H6_MIXED))
     roofline = {
         "bound": "alu",
         "achieved": achieved,
@@ -192,8 +225,7 @@ def main():
         "unit": "TFLOP/s",
         "frac": achieved / FP64_PEAK_TFLOPS,
         "traffic": traffic,
-        "kernel": ("k_eval_f64<2, %d, %d, false>" % (dom["block"], dom["ipl"]) if dom["kind"] == 0
-                   else "k_eval_small<%d, false>" % dom["ipl"]),
+        "kernel": _kernel_name(dom, prec == h6.H6_MIXED),
         "launches": dom["launches"],
         "avg_launch_us": 1e3 * dom["kernel_ms"] / max(1, dom["launches"]),
         "flops_per_launch": FLOPS_PER_INTERACTION * dom["interactions"] / max(1, dom["launches"]),

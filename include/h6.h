@@ -89,6 +89,8 @@ typedef struct {
     int lev_min;   /* largest step 2^-lev_min */
     int lev_max;   /* smallest step 2^-lev_max (below: H6_EDTMIN) */
     int precision; /* H6_FP64 or H6_MIXED for the evaluation */
+    int host_loop; /* h6_run_blocks: 0 device-resident loop, 1 one host
+                      round trip per block (h6_block_step repeated) */
 } h6_params;
 
 /* Counters filled by h6_run_blocks. */
@@ -215,8 +217,14 @@ int h6_block_step(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred,
 
 /*
  * Block steps until every particle reaches t_end (ticks, a multiple of
- * 2^-lev_min; synchronizes once per block). stats may be NULL.
- * Errors: as h6_block_step; H6_EINVAL if some t[i] > t_end.
+ * 2^-lev_min). stats may be NULL. With prm->host_loop == 0 the loop is
+ * device-resident: the scheduler publishes each block's time, active count
+ * and evaluation shape in device memory, the later kernels of the block
+ * read them there, and the host enqueues blocks in batches, waiting once
+ * per batch (synchronizes at the end). With host_loop == 1 it is
+ * h6_block_step repeated (one host round trip per block). Both give the
+ * same block sequence; the evaluation shapes (and hence last-bit rounding)
+ * may differ. Errors: as h6_block_step.
  */
 int h6_run_blocks(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred,
                   const h6_force *f, int32_t *active, const h6_params *prm,

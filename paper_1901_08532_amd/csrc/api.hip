@@ -12,6 +12,12 @@ using namespace h6;
 
 namespace {
 
+// Pinned host staging: [0, 16) block readback, [64, 68) flags,
+// [128, 168) energy, two block-loop descriptor slots.
+constexpr size_t kHostBytes = 1024;
+constexpr size_t kHostSlot0 = 512;
+constexpr size_t kHostSlot1 = 640;
+
 int fail_hip(h6_ctx ctx, hipError_t e, const char *what) {
     if (ctx) {
         char buf[256];
@@ -57,7 +63,8 @@ bool force_ok(const h6_force *f) {
 bool params_ok(const h6_params *p) {
     return p && std::isfinite(p->eta) && p->eta > 0.0 && p->lev_min >= 0 &&
            p->lev_max >= p->lev_min && p->lev_max <= kTickBits &&
-           (p->precision == H6_FP64 || p->precision == H6_MIXED);
+           (p->precision == H6_FP64 || p->precision == H6_MIXED) &&
+           (p->host_loop == 0 || p->host_loop == 1);
 }
 
 int check_n(h6_ctx ctx, int64_t n) {
@@ -103,6 +110,9 @@ int read_flags(h6_ctx ctx) {
 
 namespace h6 {
 
+static int timing_key(h6_ctx ctx, int order, int kind, int block, int ipl, int precision,
+                      int bin);
+
 hipError_t prof_begin(h6_ctx ctx, hipEvent_t *e0, hipEvent_t *e1) {
     for (hipEvent_t *e : {e0, e1}) {
         if (!ctx->event_pool.empty()) {
@@ -122,30 +132,57 @@ hipError_t prof_end(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int order, const E
     if (r != hipSuccess) return r;
     int bin = 0;
     for (int64_t na = n_act; na > 1; na >>= 1) ++bin;
-    int key = -1;
-    for (size_t q = 0; q < ctx->timings.size(); ++q) {
-        const h6_eval_timing &t = ctx->timings[q];
-        if (t.order == order && t.kind == cfg.kind && t.block == cfg.block && t.ipl == cfg.ipl &&
-            t.precision == precision && t.nact_log2 == bin)
-            key = (int)q;
-    }
-    if (key < 0) {
-        h6_eval_timing t = {order, cfg.kind, cfg.block, cfg.ipl, precision, bin, 0, 0.0, 0.0};
-        ctx->timings.push_back(t);
-        key = (int)ctx->timings.size() - 1;
-    }
-    ctx->pending.push_back({e0, e1, key, interactions});
+    const int key = timing_key(ctx, order, cfg.kind, cfg.block, cfg.ipl, precision, bin);
+    ctx->pending.push_back({e0, e1, key, interactions, -1, precision});
     return hipSuccess;
 }
 
+// Device-loop evaluation launch: its active count is known only on the
+// device; the block log (n_act per block sequence number) resolves it.
+hipError_t prof_end_seq(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int precision, int64_t seq) {
+    hipError_t r = hipEventRecord(e1, ctx->stream);
+    if (r != hipSuccess) return r;
+    ctx->pending.push_back({e0, e1, -1, 0.0, seq, precision});
+    return hipSuccess;
+}
+
+static int timing_key(h6_ctx ctx, int order, int kind, int block, int ipl, int precision,
+                      int bin) {
+    for (size_t q = 0; q < ctx->timings.size(); ++q) {
+        const h6_eval_timing &t = ctx->timings[q];
+        if (t.order == order && t.kind == kind && t.block == block && t.ipl == ipl &&
+            t.precision == precision && t.nact_log2 == bin)
+            return (int)q;
+    }
+    h6_eval_timing t = {order, kind, block, ipl, precision, bin, 0, 0.0, 0.0};
+    ctx->timings.push_back(t);
+    return (int)ctx->timings.size() - 1;
+}
+
 hipError_t prof_resolve(h6_ctx ctx) {
+    std::vector<int32_t> log;
     for (const auto &p : ctx->pending) {
         float ms = 0.0f;
         hipError_t r = hipEventElapsedTime(&ms, p.e0, p.e1);
         if (r != hipSuccess) return r;
-        h6_eval_timing &t = ctx->timings[p.key];
+        int key = p.key;
+        double inter = p.interactions;
+        if (key < 0) {
+            if (log.empty()) {
+                log.resize((size_t)ctx->bl_log_mask + 1);
+                r = hipMemcpy(log.data(), ctx->bl_log, log.size() * sizeof(int32_t),
+                              hipMemcpyDeviceToHost);
+                if (r != hipSuccess) return r;
+            }
+            const int64_t na = log[(size_t)(p.seq & ctx->bl_log_mask)];
+            int bin = -1;  // empty block (nothing evaluated)
+            for (int64_t q = na; q >= 1; q >>= 1) ++bin;
+            key = timing_key(ctx, 2, 2, 64, 2, p.precision, bin);
+            inter = (double)na * (double)ctx->bl_n;
+        }
+        h6_eval_timing &t = ctx->timings[key];
         t.launches += 1;
-        t.interactions += p.interactions;
+        t.interactions += inter;
         t.kernel_ms += ms;
         ctx->event_pool.push_back(p.e0);
         ctx->event_pool.push_back(p.e1);
@@ -195,7 +232,7 @@ int h6_create(h6_ctx *out, int64_t n_max, double eps, void *hip_stream) {
     // partial sums: n_split * ncomp * n_act doubles, n_split * n_act <= cap
     const int64_t cap_pairs = std::max<int64_t>(2 * n_max, (int64_t)1 << 21);
     ctx->partial_cap = 9 * cap_pairs;
-    ctx->sched_blocks = sched_blocks_for(n_max);
+    ctx->sched_blocks = std::max(sched_blocks_for(n_max), bl_select_blocks(n_max));
     const int64_t eb = energy_blocks_for(n_max);
     bool ok = hipMalloc(&ctx->partial, sizeof(double) * ctx->partial_cap) == hipSuccess &&
               hipMalloc(&ctx->sched64, sizeof(int64_t) * (2 + ctx->sched_blocks)) == hipSuccess &&
@@ -203,7 +240,10 @@ int h6_create(h6_ctx *out, int64_t n_max, double eps, void *hip_stream) {
               hipMalloc(&ctx->counters, sizeof(unsigned) * 8) == hipSuccess &&
               hipMalloc(&ctx->flags, sizeof(int32_t) * 4) == hipSuccess &&
               hipMalloc(&ctx->ered, sizeof(double) * (8 + 10 * eb)) == hipSuccess &&
-              hipHostMalloc(&ctx->host, 256, hipHostMallocDefault) == hipSuccess;
+              hipMalloc(&ctx->bl_desc, sizeof(BlockDesc)) == hipSuccess &&
+              hipEventCreateWithFlags(&ctx->bl_ev[0], hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&ctx->bl_ev[1], hipEventDisableTiming) == hipSuccess &&
+              hipHostMalloc(&ctx->host, kHostBytes, hipHostMallocDefault) == hipSuccess;
     if (ok) {
         ok = hipMemset(ctx->counters, 0, sizeof(unsigned) * 8) == hipSuccess &&
              hipMemset(ctx->flags, 0, sizeof(int32_t) * 4) == hipSuccess &&
@@ -228,6 +268,10 @@ int h6_destroy(h6_ctx ctx) {
     if (ctx->flags) (void)hipFree(ctx->flags);
     if (ctx->ered) (void)hipFree(ctx->ered);
     if (ctx->host) (void)hipHostFree(ctx->host);
+    if (ctx->bl_desc) (void)hipFree(ctx->bl_desc);
+    if (ctx->bl_log) (void)hipFree(ctx->bl_log);
+    for (hipEvent_t e : ctx->bl_ev)
+        if (e) (void)hipEventDestroy(e);
     for (const auto &p : ctx->pending) {
         (void)hipEventDestroy(p.e0);
         (void)hipEventDestroy(p.e1);
@@ -392,23 +436,17 @@ int h6_block_step(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred, cons
     return H6_OK;
 }
 
-int h6_run_blocks(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred, const h6_force *f,
-                  int32_t *active, const h6_params *prm, int64_t t_end, h6_run_stats *stats) {
-    if (!ctx) return H6_EINVAL;
-    if (!state_ok(st, true) || !pred_ok(pred) || !force_ok(f) || !active)
-        return fail_arg(ctx, "null pointer");
-    if (!params_ok(prm)) return fail_arg(ctx, "bad step parameters");
-    if (int rc = check_n(ctx, n)) return rc;
+// Host-sequenced loop: one host round trip (h6_next_block) per block.
+static int run_blocks_host(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred,
+                           const h6_force *f, int32_t *active, const h6_params *prm,
+                           int64_t t_end, h6_run_stats *stats) {
     h6_run_stats s = {0, 0, 0.0, 0};
     for (;;) {
         // next_block reports the smallest due time; stop once it passes t_end
         int64_t tn = 0, na = 0;
         int rc = h6_next_block(ctx, st, n, active, &tn, &na);
         if (rc) return rc;
-        if (tn > t_end) {
-            s.t_end = t_end;
-            break;
-        }
+        if (tn > t_end) break;
         H6_TRY(ctx, launch_predict(ctx, st, (int)n, tn, 0.0, false, pred), "predict");
         H6_TRY(ctx,
                launch_eval(ctx, 2, prm->precision, src_from_pred(pred, st->m), (int)n, active,
@@ -418,10 +456,70 @@ int h6_run_blocks(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred, cons
         s.blocks += 1;
         s.particle_steps += na;
         s.interactions += (double)na * (double)n;
-        s.t_end = tn;
     }
+    s.t_end = t_end;
     if (stats) *stats = s;
     return read_flags(ctx);
+}
+
+// Device-resident loop: blocks are enqueued in batches; after enqueueing
+// batch b the host waits for batch b-1 and reads its descriptor copy, so
+// the device always has a batch queued. Blocks enqueued after the last
+// one due are no-ops (their scheduler reports n_act = 0).
+static int run_blocks_device(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred,
+                             const h6_force *f, int32_t *active, const h6_params *prm,
+                             int64_t t_end, h6_run_stats *stats) {
+    ctx->bl_n = n;
+    H6_TRY(ctx, bl_reset(ctx), "block loop reset");
+    BlockDesc *slot[2] = {(BlockDesc *)((char *)ctx->host + kHostSlot0),
+                          (BlockDesc *)((char *)ctx->host + kHostSlot1)};
+    int64_t seq = 0;
+    int cur = 0;
+    bool have_prev = false;
+    int batch = 4;
+    for (;;) {
+        for (int b = 0; b < batch; ++b, ++seq)
+            H6_TRY(ctx, bl_enqueue_block(ctx, st, (int)n, pred, f, active, prm, t_end, seq),
+                   "block step");
+        H6_TRY(ctx,
+               hipMemcpyAsync(slot[cur], ctx->bl_desc, sizeof(BlockDesc), hipMemcpyDeviceToHost,
+                              ctx->stream),
+               "block status readback");
+        H6_TRY(ctx, hipEventRecord(ctx->bl_ev[cur], ctx->stream), "event record");
+        if (have_prev) {
+            H6_TRY(ctx, hipEventSynchronize(ctx->bl_ev[cur ^ 1]), "event wait");
+            if (slot[cur ^ 1]->done) break;
+        }
+        have_prev = true;
+        cur ^= 1;
+        if (batch < 64) batch *= 2;
+        if (ctx->prof && (int64_t)ctx->pending.size() > (int64_t)(ctx->bl_log_mask / 2)) {
+            // resolve before the block log ring wraps
+            H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+            H6_TRY(ctx, prof_resolve(ctx), "profile events");
+        }
+    }
+    H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    const BlockDesc d = *slot[cur];  // the copy enqueued last
+    if (!ctx->pending.empty()) H6_TRY(ctx, prof_resolve(ctx), "profile events");
+    if (stats) {
+        stats->blocks = d.blocks;
+        stats->particle_steps = d.particle_steps;
+        stats->interactions = (double)d.particle_steps * (double)n;
+        stats->t_end = t_end;
+    }
+    return read_flags(ctx);
+}
+
+int h6_run_blocks(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred, const h6_force *f,
+                  int32_t *active, const h6_params *prm, int64_t t_end, h6_run_stats *stats) {
+    if (!ctx) return H6_EINVAL;
+    if (!state_ok(st, true) || !pred_ok(pred) || !force_ok(f) || !active)
+        return fail_arg(ctx, "null pointer");
+    if (!params_ok(prm)) return fail_arg(ctx, "bad step parameters");
+    if (int rc = check_n(ctx, n)) return rc;
+    if (prm->host_loop) return run_blocks_host(ctx, st, n, pred, f, active, prm, t_end, stats);
+    return run_blocks_device(ctx, st, n, pred, f, active, prm, t_end, stats);
 }
 
 int h6_shared_steps(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred, const h6_force *f,
@@ -554,6 +652,12 @@ int h6_profile_enable(h6_ctx ctx, int on) {
     if (!ctx) return H6_EINVAL;
     H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
     H6_TRY(ctx, prof_resolve(ctx), "profile events");
+    if (on && !ctx->bl_log) {
+        const int cap = 1 << 20;
+        H6_TRY(ctx, hipMalloc(&ctx->bl_log, sizeof(int32_t) * cap), "block log");
+        H6_TRY(ctx, hipMemset(ctx->bl_log, 0, sizeof(int32_t) * cap), "block log");
+        ctx->bl_log_mask = cap - 1;
+    }
     ctx->timings.clear();
     ctx->prof = on != 0;
     return H6_OK;

@@ -1,0 +1,251 @@
+// Bodies of the mixed-precision a/j/s evaluation kernels, shared by the
+// host-shaped launches (eval_mixed.hip) and the device-resident block loop
+// (blockloop.hip). See eval_mixed.hip for the design.
+#pragma once
+
+#include "device_math.h"
+#include "h6_internal.h"
+
+namespace h6 {
+namespace mixedbody {
+
+// Far, massless padding source: contributes exactly zero; small enough that
+// its squared distance stays finite in FP32.
+constexpr double kPadPosMixed = 1.0e15;
+constexpr int kChunk = 8;  // sources per FP32 partial sum
+
+// Pair terms of order 2 in FP32, accumulated into acc[0..8] (FP32). Same
+// factorisation as the FP64 routine: A = m r/R^3, J = m w/R^3 with
+// w = v - 3 alpha r, S = m u/R^3 with u = a - 6 alpha w - 3 beta r.
+__device__ __forceinline__ void pair_acc2_f32(float dx, float dy, float dz, float dvx, float dvy,
+                                              float dvz, float dax, float day, float daz, float r2,
+                                              float mj, float *acc) {
+    // hardware estimate plus one Newton step: the estimate's own error is
+    // not centred on zero, and a common bias of every pair term would show
+    // as a secular energy drift
+    const float y = __builtin_amdgcn_rsqf(r2);
+    const float e = fmaf(-(r2 * y), y, 1.0f);
+    const float rinv = fmaf(0.5f * y, e, y);
+    const float rinv2 = rinv * rinv;
+    const float mr3 = (mj * rinv) * rinv2;
+    const float rv = fmaf(dz, dvz, fmaf(dy, dvy, dx * dvx));
+    const float alpha = rv * rinv2;
+    const float a3 = 3.0f * alpha;
+    const float wx = fmaf(-a3, dx, dvx), wy = fmaf(-a3, dy, dvy), wz = fmaf(-a3, dz, dvz);
+    const float vvra =
+        fmaf(dz, daz, fmaf(dy, day, fmaf(dx, dax, fmaf(dvz, dvz, fmaf(dvy, dvy, dvx * dvx)))));
+    const float beta = fmaf(alpha, alpha, vvra * rinv2);
+    const float b3 = 3.0f * beta;
+    const float a6 = a3 + a3;
+    const float ux = fmaf(-a6, wx, fmaf(-b3, dx, dax));
+    const float uy = fmaf(-a6, wy, fmaf(-b3, dy, day));
+    const float uz = fmaf(-a6, wz, fmaf(-b3, dz, daz));
+    acc[0] = fmaf(mr3, dx, acc[0]);
+    acc[1] = fmaf(mr3, dy, acc[1]);
+    acc[2] = fmaf(mr3, dz, acc[2]);
+    acc[3] = fmaf(mr3, wx, acc[3]);
+    acc[4] = fmaf(mr3, wy, acc[4]);
+    acc[5] = fmaf(mr3, wz, acc[5]);
+    acc[6] = fmaf(mr3, ux, acc[6]);
+    acc[7] = fmaf(mr3, uy, acc[7]);
+    acc[8] = fmaf(mr3, uz, acc[8]);
+}
+
+// LDS source record: x0 x1 | x2 v0 | v1 v2 (FP64), then a0 a1 a2 m (FP32).
+struct alignas(16) RecMixed {
+    double2 p0, p1, p2;
+    float4 am;
+};
+
+// Body for the workgroup owning target block ib and source slice sl.
+template <int BLOCK, int IPL, bool SKIPSELF>
+__device__ __forceinline__ void mixed_tile_body(const SrcPtrs &src,
+                                                const int32_t *__restrict__ active, int n,
+                                                int n_act, double eps2, int slice_len,
+                                                const OutPtrs &out, int64_t slice_stride, int ib,
+                                                int sl) {
+    __shared__ RecMixed tile[BLOCK];
+    const int tid = threadIdx.x;
+    const float eps2f = (float)eps2;
+
+    double xi[IPL][3], vi[IPL][3];
+    float ai[IPL][3];
+    int pid[IPL], kid[IPL];
+#pragma unroll
+    for (int u = 0; u < IPL; ++u) {
+        const int k = (ib * IPL + u) * BLOCK + tid;
+        kid[u] = k;
+        const int kc = k < n_act ? k : n_act - 1;
+        const int p = active ? active[kc] : kc;
+        pid[u] = p;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            xi[u][c] = src.x[c][p];
+            vi[u][c] = src.v[c][p];
+            ai[u][c] = (float)src.a[c][p];
+        }
+    }
+    double acc[IPL][9], hi[IPL][9], lo[IPL][9];
+#pragma unroll
+    for (int u = 0; u < IPL; ++u)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc[u][q] = hi[u][q] = lo[u][q] = 0.0;
+
+    const int jb = sl * slice_len;
+    const int je = min(n, jb + slice_len);
+    for (int jt = jb; jt < je; jt += BLOCK) {
+        __syncthreads();
+        {
+            const int jj = jt + tid;
+            RecMixed r;
+            if (jj < je) {
+                r.p0 = make_double2(src.x[0][jj], src.x[1][jj]);
+                r.p1 = make_double2(src.x[2][jj], src.v[0][jj]);
+                r.p2 = make_double2(src.v[1][jj], src.v[2][jj]);
+                r.am = make_float4((float)src.a[0][jj], (float)src.a[1][jj], (float)src.a[2][jj],
+                                   (float)src.m[jj]);
+            } else {
+                r.p0 = make_double2(kPadPosMixed, kPadPosMixed);
+                r.p1 = make_double2(kPadPosMixed, 0.0);
+                r.p2 = make_double2(0.0, 0.0);
+                r.am = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            tile[tid] = r;
+        }
+        __syncthreads();
+
+        for (int q0 = 0; q0 < BLOCK; q0 += kChunk) {
+            float acc32[IPL][9];
+#pragma unroll
+            for (int u = 0; u < IPL; ++u)
+#pragma unroll
+                for (int q = 0; q < 9; ++q) acc32[u][q] = 0.0f;
+#pragma unroll
+            for (int qq = 0; qq < kChunk; ++qq) {
+                const RecMixed r = tile[q0 + qq];
+#pragma unroll
+                for (int u = 0; u < IPL; ++u) {
+                    const float dx = (float)(r.p0.x - xi[u][0]);
+                    const float dy = (float)(r.p0.y - xi[u][1]);
+                    const float dz = (float)(r.p1.x - xi[u][2]);
+                    const float dvx = (float)(r.p1.y - vi[u][0]);
+                    const float dvy = (float)(r.p2.x - vi[u][1]);
+                    const float dvz = (float)(r.p2.y - vi[u][2]);
+                    float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2f)));
+                    float m_eff = r.am.w;
+                    if (SKIPSELF) {
+                        const bool self = (jt + q0 + qq) == pid[u];
+                        r2 = self ? 1.0f : r2;
+                        m_eff = self ? 0.0f : m_eff;
+                    }
+                    pair_acc2_f32(dx, dy, dz, dvx, dvy, dvz, r.am.x - ai[u][0], r.am.y - ai[u][1],
+                                  r.am.z - ai[u][2], r2, m_eff, acc32[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < IPL; ++u)
+#pragma unroll
+                for (int q = 0; q < 9; ++q) acc[u][q] += (double)acc32[u][q];
+        }
+#pragma unroll
+        for (int u = 0; u < IPL; ++u)
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                two_sum_into(hi[u][q], lo[u][q], acc[u][q]);
+                acc[u][q] = 0.0;
+            }
+    }
+    const int64_t soff = (int64_t)sl * slice_stride;
+#pragma unroll
+    for (int u = 0; u < IPL; ++u)
+        if (kid[u] < n_act)
+#pragma unroll
+            for (int q = 0; q < 9; ++q) out.p[q][soff + kid[u]] = hi[u][q] + lo[u][q];
+}
+
+// Small active sets: lanes over sources, TPW targets per wave (as the FP64
+// source-parallel kernel), FP32 pair arithmetic, FP32 partial sums over
+// kChunk sources per lane flushed into compensated FP64 pairs.
+template <int TPW, bool SKIPSELF>
+__device__ __forceinline__ void mixed_small_body(const SrcPtrs &src,
+                                                 const int32_t *__restrict__ active, int n,
+                                                 int n_act, double eps2, int slice_len,
+                                                 const OutPtrs &out, int64_t slice_stride,
+                                                 int wave, int sl) {
+    const int lane = threadIdx.x & 63;
+    const float eps2f = (float)eps2;
+    double xi[TPW][3], vi[TPW][3];
+    float ai[TPW][3];
+    int pid[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        int k = wave * TPW + t;
+        k = k < n_act ? k : n_act - 1;
+        const int p = active ? active[k] : k;
+        pid[t] = p;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            xi[t][c] = src.x[c][p];
+            vi[t][c] = src.v[c][p];
+            ai[t][c] = (float)src.a[c][p];
+        }
+    }
+    float acc32[TPW][9];
+    double hi[TPW][9], lo[TPW][9];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            acc32[t][q] = 0.0f;
+            hi[t][q] = lo[t][q] = 0.0;
+        }
+    const int jb = sl * slice_len;
+    const int je = min(n, jb + slice_len);
+    int since_flush = 0;
+    for (int j = jb + lane; j < je; j += 64) {
+        const double xj0 = src.x[0][j], xj1 = src.x[1][j], xj2 = src.x[2][j];
+        const double vj0 = src.v[0][j], vj1 = src.v[1][j], vj2 = src.v[2][j];
+        const float aj0 = (float)src.a[0][j], aj1 = (float)src.a[1][j], aj2 = (float)src.a[2][j];
+        const float mj = (float)src.m[j];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            const float dx = (float)(xj0 - xi[t][0]), dy = (float)(xj1 - xi[t][1]),
+                        dz = (float)(xj2 - xi[t][2]);
+            float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2f)));
+            float m_eff = mj;
+            if (SKIPSELF) {
+                const bool self = j == pid[t];
+                r2 = self ? 1.0f : r2;
+                m_eff = self ? 0.0f : mj;
+            }
+            pair_acc2_f32(dx, dy, dz, (float)(vj0 - vi[t][0]), (float)(vj1 - vi[t][1]),
+                          (float)(vj2 - vi[t][2]), aj0 - ai[t][0], aj1 - ai[t][1], aj2 - ai[t][2],
+                          r2, m_eff, acc32[t]);
+        }
+        if (++since_flush == kChunk) {
+            since_flush = 0;
+#pragma unroll
+            for (int t = 0; t < TPW; ++t)
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    two_sum_into(hi[t][q], lo[t][q], (double)acc32[t][q]);
+                    acc32[t][q] = 0.0f;
+                }
+        }
+    }
+    const int64_t soff = (int64_t)sl * slice_stride;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            two_sum_into(hi[t][q], lo[t][q], (double)acc32[t][q]);
+            double sv = hi[t][q], cv = lo[t][q];
+            wave_comp_sum(sv, cv);
+            const int k = wave * TPW + t;
+            if (lane == 0 && k < n_act) out.p[q][soff + k] = sv + cv;
+        }
+    }
+}
+
+}  // namespace mixedbody
+}  // namespace h6

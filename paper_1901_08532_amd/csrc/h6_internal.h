@@ -32,6 +32,20 @@ struct OutPtrs {
     double *p[kMaxOut];
 };
 
+// Per-block descriptor of the device-resident block loop, written by the
+// scheduler's last workgroup and read by the later kernels of the block.
+struct BlockDesc {
+    int64_t t_next;     // block time (ticks)
+    int32_t n_act;      // active particles; 0 = nothing to do
+    int32_t done;       // 1 once t_next would pass t_end
+    int32_t kind;       // evaluation kind: 0 tile, 1 source-parallel
+    int32_t groups;     // target groups (tile: 128 targets; source-parallel: 1)
+    int32_t split;      // source slices
+    int32_t slice_len;  // sources per slice
+    int64_t blocks;     // non-empty blocks since the loop started
+    int64_t particle_steps;  // sum of n_act since the loop started
+};
+
 struct EvalConfig {
     int kind;    // 0: LDS-tiled target-parallel kernel; 1: source-parallel small-set kernel
     int block;   // threads per workgroup
@@ -61,11 +75,19 @@ struct h6_ctx_s {
     // pinned host staging for scheduler/energy readback
     void *host = nullptr;
     std::string last_error;
+    // device-resident block loop
+    h6::BlockDesc *bl_desc = nullptr;  // device
+    int32_t *bl_log = nullptr;     // n_act per block sequence number (ring), profiling only
+    int bl_log_mask = 0;
+    hipEvent_t bl_ev[2] = {nullptr, nullptr};
+    int64_t bl_n = 0;              // particle count of the current loop (profiling)
     // measurement hook (h6_profile_enable)
     struct PendingTiming {
         hipEvent_t e0, e1;
-        int key;
+        int key;             // timing record, or -1: resolve through the block log
         double interactions;
+        int64_t seq;         // block sequence number (device loop)
+        int precision;
     };
     bool prof = false;
     std::vector<hipEvent_t> event_pool;
@@ -114,7 +136,16 @@ int sched_blocks_for(int64_t n);
 hipError_t prof_begin(h6_ctx ctx, hipEvent_t *e0, hipEvent_t *e1);
 hipError_t prof_end(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int order, const EvalConfig &cfg,
                     int precision, int64_t n_act, double interactions);
+hipError_t prof_end_seq(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int precision, int64_t seq);
 hipError_t prof_resolve(h6_ctx ctx);  // stream must be idle
+
+// Device-resident block loop (blockloop.hip).
+int bl_select_blocks(int64_t n);
+int bl_eval_grid(h6_ctx ctx);
+hipError_t bl_reset(h6_ctx ctx);
+hipError_t bl_enqueue_block(h6_ctx ctx, h6_state *st, int n, const h6_pred *pred,
+                            const h6_force *f, int32_t *active, const h6_params *prm,
+                            int64_t t_end, int64_t seq);
 int energy_blocks_for(int64_t n);
 
 }  // namespace h6

@@ -44,7 +44,7 @@ class h6_force(C.Structure):
 
 class h6_params(C.Structure):
     _fields_ = [("eta", C.c_double), ("lev_min", C.c_int), ("lev_max", C.c_int),
-                ("precision", C.c_int)]
+                ("precision", C.c_int), ("host_loop", C.c_int)]
 
 
 class h6_run_stats(C.Structure):
@@ -240,7 +240,7 @@ class Context:
     def h6_correct(self, S, m, T, active, n_act, F, t_next, eta, lev_min, lev_max,
                    precision=H6_FP64):
         st, fo = make_state(S, m, T), make_force(F)
-        prm = h6_params(float(eta), int(lev_min), int(lev_max), int(precision))
+        prm = h6_params(float(eta), int(lev_min), int(lev_max), int(precision), 0)
         return self._check(lib().h6_correct(self._h, C.byref(st), _ptr(active), int(n_act),
                                             C.byref(fo), int(t_next), C.byref(prm)), "h6_correct")
 
@@ -267,7 +267,7 @@ class Context:
 
     def h6_block_step(self, S, m, T, P, F, active, eta, lev_min, lev_max, precision=H6_FP64):
         st, pr, fo = make_state(S, m, T), make_pred(P), make_force(F)
-        prm = h6_params(float(eta), int(lev_min), int(lev_max), int(precision))
+        prm = h6_params(float(eta), int(lev_min), int(lev_max), int(precision), 0)
         tn, na = C.c_int64(), C.c_int64()
         self._check(lib().h6_block_step(self._h, C.byref(st), S.shape[1], C.byref(pr), C.byref(fo),
                                         _ptr(active), C.byref(prm), C.byref(tn), C.byref(na)),
@@ -275,9 +275,10 @@ class Context:
         return tn.value, na.value
 
     def h6_run_blocks(self, S, m, T, P, F, active, eta, lev_min, lev_max, t_end,
-                      precision=H6_FP64, check=True):
+                      precision=H6_FP64, check=True, host_loop=False):
         st, pr, fo = make_state(S, m, T), make_pred(P), make_force(F)
-        prm = h6_params(float(eta), int(lev_min), int(lev_max), int(precision))
+        prm = h6_params(float(eta), int(lev_min), int(lev_max), int(precision),
+                        1 if host_loop else 0)
         stats = h6_run_stats()
         rc = lib().h6_run_blocks(self._h, C.byref(st), S.shape[1], C.byref(pr), C.byref(fo),
                                  _ptr(active), C.byref(prm), int(t_end), C.byref(stats))
@@ -377,9 +378,10 @@ class System:
         return self.ctx.h6_block_step(self.S, self.m, self.T, self.P, self.F, self.active, eta,
                                       lev_min, lev_max, precision)
 
-    def run_blocks(self, t_end_ticks, eta, lev_min, lev_max, precision=H6_FP64, check=True):
+    def run_blocks(self, t_end_ticks, eta, lev_min, lev_max, precision=H6_FP64, check=True,
+                   host_loop=False):
         return self.ctx.h6_run_blocks(self.S, self.m, self.T, self.P, self.F, self.active, eta,
-                                      lev_min, lev_max, t_end_ticks, precision, check)
+                                      lev_min, lev_max, t_end_ticks, precision, check, host_loop)
 
     def energy(self):
         return self.ctx.h6_energy(self.S, self.m)

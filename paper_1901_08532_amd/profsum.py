@@ -19,7 +19,17 @@ import re
 from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-EVAL_SOURCE = os.path.join(ROOT, "paper_1901_08532_amd", "csrc", "eval.hip")
+CSRC = os.path.join(ROOT, "paper_1901_08532_amd", "csrc")
+# the evaluation kernels' sources (the same list as bench.py checks)
+EVAL_SOURCES = ("eval_body.h", "eval_mixed_body.h", "device_math.h", "blockloop.hip", "eval.hip",
+                "eval_mixed.hip")
+
+
+def eval_sources_sha256():
+    h = hashlib.sha256()
+    for f in EVAL_SOURCES:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()
 
 
 def _short(name):
@@ -73,7 +83,7 @@ def traffic(fetch_csv, write_csv, copy_bytes, match=None):
     print("copy_write_kib = %.1f" % cw)
     print("fetch_scale = %.6f" % f_scale)
     print("write_scale = %.6f" % w_scale)
-    print("eval_source_sha256 = %s" % hashlib.sha256(open(EVAL_SOURCE, "rb").read()).hexdigest())
+    print("eval_source_sha256 = %s" % eval_sources_sha256())
     for k in sorted(fetch):
         if match and match not in k:
             continue
@@ -82,7 +92,14 @@ def traffic(fetch_csv, write_csv, copy_bytes, match=None):
         fb = sum(fv) / len(fv) * 1024.0 * f_scale
         wb = sum(wv) / len(wv) * 1024.0 * w_scale
         m = re.search(r"k_eval_f64<2, (\d+), (\d+), false>", k)
-        tag = "b%s_i%s" % (m.group(1), m.group(2)) if m else re.sub(r"\W+", "_", k)[:60]
+        if m:
+            tag = "b%s_i%s" % (m.group(1), m.group(2))
+        elif "k_bl_eval<false, false>" in k:
+            tag = "bl_eval_fp64"
+        elif "k_bl_eval<true, false>" in k:
+            tag = "bl_eval_mixed"
+        else:
+            tag = re.sub(r"\W+", "_", k)[:60]
         print("# %s: %d dispatches" % (k, len(fv)))
         print("fetch_bytes_per_launch_%s = %.1f" % (tag, fb))
         print("write_bytes_per_launch_%s = %.1f" % (tag, wb))

@@ -1,0 +1,117 @@
+"""The device-resident block loop (h6_run_blocks, host_loop = 0).
+
+It must take the same blocks as the host-sequenced loop and as the oracle
+(block times and active counts bit-exact, steps bit-exact), and agree with
+them on the state to rounding; empty runs and awkward sizes included.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1901_08532_amd import h6, ics
+from _gpu import DEV, vec_rel_err
+
+pytestmark = pytest.mark.gpu
+
+TB = h6.TICK_BITS
+EPS = 1e-4
+SYNC = 1 << (TB - 4)
+
+
+def _from_oracle(st):
+    sysg = h6.System(st.x, st.v, st.m, math.sqrt(st.eps2))
+    for k, name in enumerate(("x", "v", "a", "j", "s", "c")):
+        sysg.S[3 * k:3 * k + 3] = torch.from_numpy(np.ascontiguousarray(getattr(st, name).T)).to(DEV)
+    sysg.T[0] = torch.from_numpy(st.t).to(DEV)
+    sysg.T[1] = torch.from_numpy(st.dt).to(DEV)
+    return sysg
+
+
+@pytest.mark.parametrize("n", [33, 1000, 5000])
+def test_device_loop_matches_oracle_blocks(n):
+    x, v, m = ics.plummer(n, 100 + n)
+    st = oracle.State(x, v, m, EPS ** 2)
+    assert st.startup(eta_s=0.1, lev_min=4, lev_max=30) == 0
+    sysg = _from_oracle(st)
+    nblk = psteps = 0
+    while True:
+        rc, tn, na = st.block_step(0.4, 4, 30)
+        assert rc == 0
+        nblk += 1
+        psteps += na
+        if tn == SYNC and np.all(st.t == SYNC):
+            break
+    rc, stats = sysg.run_blocks(SYNC, 0.4, 4, 30)
+    assert rc == h6.H6_OK
+    assert (stats.blocks, stats.particle_steps) == (nblk, psteps)
+    assert stats.interactions == float(psteps) * n
+    assert np.array_equal(sysg.T.cpu().numpy(), np.stack([st.t, st.dt]))
+    for name in ("x", "v", "a", "j", "s"):
+        assert vec_rel_err(sysg.field(name), getattr(st, name)).max() < 1e-9, name
+
+
+@pytest.mark.parametrize("precision", [h6.H6_FP64, h6.H6_MIXED])
+def test_device_loop_matches_host_loop(precision):
+    n = 20000
+    x, v, m = ics.plummer(n, 7)
+    a = h6.System(x, v, m, EPS)
+    a.startup(eta_s=0.1, lev_min=4, lev_max=30)
+    b = h6.System(x, v, m, EPS)
+    b.S.copy_(a.S)
+    b.T.copy_(a.T)
+    for k in range(2):
+        ra, sa = a.run_blocks((k + 1) * SYNC, 0.4, 4, 30, precision)
+        rb, sb = b.run_blocks((k + 1) * SYNC, 0.4, 4, 30, precision, host_loop=True)
+        assert ra == rb == h6.H6_OK
+        if precision == h6.H6_FP64:
+            assert (sa.blocks, sa.particle_steps) == (sb.blocks, sb.particle_steps)
+        else:
+            # FP32 partial sums group differently under the two launch shapes;
+            # forces then differ at ~1e-7 and a step decision within that of a
+            # power of two may flip for a handful of particles
+            assert abs(sa.particle_steps - sb.particle_steps) <= 1e-4 * sb.particle_steps
+    if precision == h6.H6_FP64:
+        assert torch.equal(a.T, b.T)
+        for name in ("x", "v", "a", "j", "s"):
+            assert vec_rel_err(a.field(name), b.field(name)).max() < 1e-9, name
+    else:
+        assert (a.T != b.T).any(dim=0).sum().item() <= 1e-3 * n
+        for name in ("x", "v"):
+            assert np.median(vec_rel_err(a.field(name), b.field(name))) < 1e-6, name
+        ea, eb = sum(a.energy()[:2]), sum(b.energy()[:2])
+        assert abs(ea - eb) < 1e-9 * abs(eb)
+
+
+def test_device_loop_nothing_due_and_repeat():
+    n = 3000
+    x, v, m = ics.plummer(n, 9)
+    s = h6.System(x, v, m, EPS)
+    s.startup(eta_s=0.1, lev_min=4, lev_max=30)
+    rc, st = s.run_blocks(SYNC, 0.4, 4, 30)
+    assert rc == h6.H6_OK and st.blocks > 0
+    T1 = s.T.clone()
+    S1 = s.S.clone()
+    rc, st = s.run_blocks(SYNC, 0.4, 4, 30)  # already there: no block
+    assert rc == h6.H6_OK and st.blocks == 0 and st.particle_steps == 0
+    assert torch.equal(s.T, T1) and torch.equal(s.S, S1)
+
+
+def test_device_loop_profile_records():
+    n = 8192
+    x, v, m = ics.plummer(n, 11)
+    s = h6.System(x, v, m, EPS)
+    s.startup(eta_s=0.1, lev_min=4, lev_max=30)
+    s.ctx.h6_profile_enable(True)
+    rc, st = s.run_blocks(SYNC, 0.4, 4, 30)
+    recs = s.ctx.h6_profile_read()
+    s.ctx.h6_profile_enable(False)
+    assert rc == h6.H6_OK
+    loop = [r for r in recs if r["kind"] == 2]
+    real = [r for r in loop if r["nact_log2"] >= 0]
+    assert sum(r["launches"] for r in real) == st.blocks
+    assert sum(r["interactions"] for r in real) == pytest.approx(st.interactions)
+    assert all(r["kernel_ms"] > 0 for r in real)
