@@ -3,6 +3,12 @@
   python -m paper_1901_08532_amd.profsum stats <kernel_stats.csv> [--match SUBSTR]
       per-kernel calls, average and total duration
 
+  python -m paper_1901_08532_amd.profsum counters <counter_collection.csv> --match K
+      --interactions I
+      the largest dispatches of kernel K: each counter, VALU/LDS instructions
+      per interaction (for I interactions per dispatch), executed FP64 flops
+      and the clock from GRBM_GUI_ACTIVE
+
   python -m paper_1901_08532_amd.profsum traffic <fetch counter_collection.csv>
       <write counter_collection.csv> --copy-bytes B [--match SUBSTR]
       HBM bytes per dispatch of each matching kernel from FETCH_SIZE and
@@ -106,6 +112,41 @@ def traffic(fetch_csv, write_csv, copy_bytes, match=None):
         print("hbm_bytes_per_launch_%s = %.1f" % (tag, fb + wb))
 
 
+def counters(path, match, interactions):
+    """Per-dispatch counters of the largest dispatches of a kernel (by
+    SQ_INSTS_VALU_FMA_F64), as instructions per interaction for a dispatch
+    of `interactions` pair interactions, and the clock from GRBM_GUI_ACTIVE."""
+    per = defaultdict(dict)
+    meta = {}
+    for r in csv.DictReader(open(path)):
+        if match not in r["Kernel_Name"]:
+            continue
+        d = r["Dispatch_Id"]
+        per[d][r["Counter_Name"]] = per[d].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        meta[d] = (int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+    key = "SQ_INSTS_VALU_FMA_F64" if any("SQ_INSTS_VALU_FMA_F64" in v for v in per.values()) else None
+    top = sorted(per, key=lambda d: -per[d].get(key, 0.0) if key else 0.0)[:3]
+    for d in top:
+        c = per[d]
+        dur = (meta[d][1] - meta[d][0]) * 1e-9
+        print("# dispatch %s: %.3f ms" % (d, dur * 1e3))
+        for name in sorted(c):
+            v = c[name]
+            line = "%-28s %16.0f" % (name, v)
+            if name.startswith("SQ_INSTS_VALU") or name.startswith("SQ_INSTS_LDS"):
+                line += "   %8.3f wave-instr x64 / interaction" % (v * 64.0 / interactions)
+            if name == "GRBM_GUI_ACTIVE" and dur > 0:
+                line += "   %.3f GHz" % (v / dur * 1e-9)
+            print(line)
+        if key and all(k in c for k in ("SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64",
+                                        "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_TRANS_F64")):
+            ex = 64.0 * (2 * c["SQ_INSTS_VALU_FMA_F64"] + c["SQ_INSTS_VALU_ADD_F64"]
+                         + c["SQ_INSTS_VALU_MUL_F64"] + c["SQ_INSTS_VALU_TRANS_F64"])
+            print("executed FP64 flops per interaction (FMA 2, ADD/MUL/TRANS 1) = %.2f" % (ex / interactions))
+            if dur > 0:
+                print("executed FP64 rate = %.2f TFLOP/s" % (ex / dur * 1e-12))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -117,9 +158,15 @@ def main():
     b.add_argument("write_csv")
     b.add_argument("--copy-bytes", type=int, required=True)
     b.add_argument("--match")
+    c = sub.add_parser("counters")
+    c.add_argument("csv")
+    c.add_argument("--match", required=True)
+    c.add_argument("--interactions", type=float, required=True)
     args = ap.parse_args()
     if args.cmd == "stats":
         stats(args.csv, args.match)
+    elif args.cmd == "counters":
+        counters(args.csv, args.match, args.interactions)
     else:
         traffic(args.fetch_csv, args.write_csv, args.copy_bytes, args.match)
 
