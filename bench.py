@@ -43,8 +43,8 @@ FP32_PEAK_TFLOPS = 157.3
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eval_hbm_traffic.txt")
 CSRC = os.path.join(ROOT, "paper_1901_08532_amd", "csrc")
 # the evaluation kernels' sources: the traffic record is void once any changes
-EVAL_SOURCES = ("eval_body.h", "eval_mixed_body.h", "device_math.h", "blockloop.hip", "eval.hip",
-                "eval_mixed.hip")
+EVAL_SOURCES = ("eval_body.h", "eval_mixed_body.h", "device_math.h", "steps_body.h",
+                "blockloop.hip", "eval.hip", "eval_mixed.hip")
 
 
 def _log(msg):

@@ -216,15 +216,31 @@ int h6_block_step(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred,
                   int64_t *t_next, int64_t *n_act);
 
 /*
- * Block steps until every particle reaches t_end (ticks, a multiple of
- * 2^-lev_min). stats may be NULL. With prm->host_loop == 0 the loop is
- * device-resident: the scheduler publishes each block's time, active count
- * and evaluation shape in device memory, the later kernels of the block
- * read them there, and the host enqueues blocks in batches, waiting once
- * per batch (synchronizes at the end). With host_loop == 1 it is
- * h6_block_step repeated (one host round trip per block). Both give the
- * same block sequence; the evaluation shapes (and hence last-bit rounding)
- * may differ. Errors: as h6_block_step.
+ * Block steps (Sec. 2 block time steps) until every particle reaches t_end
+ * (ticks, a multiple of 2^-lev_min). stats may be NULL. Synchronizes at the
+ * end.
+ *
+ * prm->host_loop == 1: h6_block_step repeated (one host round trip per
+ * block).
+ *
+ * prm->host_loop == 0: device-resident loop. The particles are kept in
+ * per-level lists on the device; each block's plan (time, active levels
+ * and count, evaluation shape) is made on the device by the block before,
+ * so the host only enqueues blocks in batches and waits once per batch.
+ * This needs every particle on the block grid -- its step a power of two
+ * between 2^-lev_max and 2^-lev_min and its time a multiple of its step,
+ * no later than any particle's time plus step -- which holds after
+ * h6_initial_steps and after any block steps with the same levels; a state
+ * that is not on the grid is run with the host loop instead (same results).
+ * The lists take 8 * (lev_max - lev_min + 1) * n bytes of device memory,
+ * allocated by the first call that needs them and kept by the context
+ * (H6_ENOMEM if that fails). pred and f are used as work arrays; the
+ * device loop writes no forces to f.
+ *
+ * Both loops take the same block sequence; the evaluation shapes (and
+ * hence last-bit rounding) may differ. Errors: as h6_block_step; H6_ESTATE
+ * if the device loop's list bookkeeping ever went out of range (an
+ * internal error, reported instead of acted on).
  */
 int h6_run_blocks(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred,
                   const h6_force *f, int32_t *active, const h6_params *prm,

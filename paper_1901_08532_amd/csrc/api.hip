@@ -14,9 +14,11 @@ namespace {
 
 // Pinned host staging: [0, 16) block readback, [64, 68) flags,
 // [128, 168) energy, two block-loop descriptor slots.
-constexpr size_t kHostBytes = 1024;
-constexpr size_t kHostSlot0 = 512;
-constexpr size_t kHostSlot1 = 640;
+constexpr size_t kHostBytes = 2048;
+constexpr size_t kHostSlot0 = 1024;
+constexpr size_t kHostSlot1 = 1536;
+static_assert(sizeof(LoopDesc) <= kHostSlot1 - kHostSlot0 && kHostSlot1 + sizeof(LoopDesc) <= kHostBytes,
+              "descriptor slots");
 
 int fail_hip(h6_ctx ctx, hipError_t e, const char *what) {
     if (ctx) {
@@ -101,6 +103,10 @@ int read_flags(h6_ctx ctx) {
            "flag readback");
     H6_TRY(ctx, hipMemsetAsync(ctx->flags, 0, sizeof(int32_t), ctx->stream), "flag reset");
     H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    if (h[0] & kFlagLoop) {
+        ctx->last_error = "block loop: level-list index out of range";
+        return H6_ESTATE;
+    }
     if (h[0] & kFlagNonFinite) return H6_ENONFINITE;
     if (h[0] & kFlagDtMin) return H6_EDTMIN;
     return H6_OK;
@@ -113,16 +119,23 @@ namespace h6 {
 static int timing_key(h6_ctx ctx, int order, int kind, int block, int ipl, int precision,
                       int bin);
 
-hipError_t prof_begin(h6_ctx ctx, hipEvent_t *e0, hipEvent_t *e1) {
+hipError_t prof_events(h6_ctx ctx, hipEvent_t *e0, hipEvent_t *e1) {
     for (hipEvent_t *e : {e0, e1}) {
         if (!ctx->event_pool.empty()) {
             *e = ctx->event_pool.back();
             ctx->event_pool.pop_back();
         } else {
-            hipError_t r = hipEventCreate(e);
+            // timestamps only: no system-scope cache flush at the marker
+            hipError_t r = hipEventCreateWithFlags(e, hipEventDisableSystemFence);
             if (r != hipSuccess) return r;
         }
     }
+    return hipSuccess;
+}
+
+hipError_t prof_begin(h6_ctx ctx, hipEvent_t *e0, hipEvent_t *e1) {
+    hipError_t r = prof_events(ctx, e0, e1);
+    if (r != hipSuccess) return r;
     return hipEventRecord(*e0, ctx->stream);
 }
 
@@ -139,9 +152,7 @@ hipError_t prof_end(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int order, const E
 
 // Device-loop evaluation launch: its active count is known only on the
 // device; the block log (n_act per block sequence number) resolves it.
-hipError_t prof_end_seq(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int precision, int64_t seq) {
-    hipError_t r = hipEventRecord(e1, ctx->stream);
-    if (r != hipSuccess) return r;
+hipError_t prof_push_seq(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int precision, int64_t seq) {
     ctx->pending.push_back({e0, e1, -1, 0.0, seq, precision});
     return hipSuccess;
 }
@@ -232,7 +243,7 @@ int h6_create(h6_ctx *out, int64_t n_max, double eps, void *hip_stream) {
     // partial sums: n_split * ncomp * n_act doubles, n_split * n_act <= cap
     const int64_t cap_pairs = std::max<int64_t>(2 * n_max, (int64_t)1 << 21);
     ctx->partial_cap = 9 * cap_pairs;
-    ctx->sched_blocks = std::max(sched_blocks_for(n_max), bl_select_blocks(n_max));
+    ctx->sched_blocks = sched_blocks_for(n_max);
     const int64_t eb = energy_blocks_for(n_max);
     bool ok = hipMalloc(&ctx->partial, sizeof(double) * ctx->partial_cap) == hipSuccess &&
               hipMalloc(&ctx->sched64, sizeof(int64_t) * (2 + ctx->sched_blocks)) == hipSuccess &&
@@ -240,7 +251,8 @@ int h6_create(h6_ctx *out, int64_t n_max, double eps, void *hip_stream) {
               hipMalloc(&ctx->counters, sizeof(unsigned) * 8) == hipSuccess &&
               hipMalloc(&ctx->flags, sizeof(int32_t) * 4) == hipSuccess &&
               hipMalloc(&ctx->ered, sizeof(double) * (8 + 10 * eb)) == hipSuccess &&
-              hipMalloc(&ctx->bl_desc, sizeof(BlockDesc)) == hipSuccess &&
+              hipMalloc(&ctx->bl_desc, 2 * sizeof(LoopDesc)) == hipSuccess &&
+              hipMalloc(&ctx->bl_scr, sizeof(LoopScratch)) == hipSuccess &&
               hipEventCreateWithFlags(&ctx->bl_ev[0], hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&ctx->bl_ev[1], hipEventDisableTiming) == hipSuccess &&
               hipHostMalloc(&ctx->host, kHostBytes, hipHostMallocDefault) == hipSuccess;
@@ -269,6 +281,8 @@ int h6_destroy(h6_ctx ctx) {
     if (ctx->ered) (void)hipFree(ctx->ered);
     if (ctx->host) (void)hipHostFree(ctx->host);
     if (ctx->bl_desc) (void)hipFree(ctx->bl_desc);
+    if (ctx->bl_scr) (void)hipFree(ctx->bl_scr);
+    if (ctx->bl_lists) (void)hipFree(ctx->bl_lists);
     if (ctx->bl_log) (void)hipFree(ctx->bl_log);
     for (hipEvent_t e : ctx->bl_ev)
         if (e) (void)hipEventDestroy(e);
@@ -462,28 +476,73 @@ static int run_blocks_host(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *p
     return read_flags(ctx);
 }
 
-// Device-resident loop: blocks are enqueued in batches; after enqueueing
-// batch b the host waits for batch b-1 and reads its descriptor copy, so
-// the device always has a batch queued. Blocks enqueued after the last
-// one due are no-ops (their scheduler reports n_act = 0).
+// Device-resident loop: a set-up pass builds the level lists and plans
+// block 0 (one readback: a state off the block grid goes to the host loop);
+// then blocks are enqueued in batches, and after enqueueing batch b the host
+// waits for batch b-1 and reads its descriptor copy, so the device always
+// has a batch queued. Blocks enqueued after the last one due are no-ops.
 static int run_blocks_device(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred,
                              const h6_force *f, int32_t *active, const h6_params *prm,
                              int64_t t_end, h6_run_stats *stats) {
+    const int nl = prm->lev_max - prm->lev_min + 1;
+    const int64_t need = bl_list_ints(n, nl);
+    if (ctx->bl_lists_cap < need) {
+        H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+        if (ctx->bl_lists) H6_TRY(ctx, hipFree(ctx->bl_lists), "free level lists");
+        ctx->bl_lists = nullptr;
+        ctx->bl_lists_cap = 0;
+        if (hipMalloc(&ctx->bl_lists, sizeof(int32_t) * need) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->bl_lists = nullptr;
+            ctx->last_error = "level lists: out of device memory";
+            return H6_ENOMEM;
+        }
+        ctx->bl_lists_cap = need;
+    }
+    LoopArgs A;
+    A.st = *st;
+    A.n = (int)n;
+    A.lev_lo = prm->lev_min;
+    A.nl = nl;
+    A.lists = ctx->bl_lists;
+    A.desc = ctx->bl_desc;
+    A.scr = ctx->bl_scr;
+    A.partial = ctx->partial;
+    A.pred = *pred;
+    A.eps2 = ctx->eps2;
+    const double e2 = prm->eta * prm->eta;
+    A.eta6 = e2 * e2 * e2;
+    A.lev_min = prm->lev_min;
+    A.lev_max = prm->lev_max;
+    A.t_end = t_end;
+    A.eval_grid = bl_eval_grid(ctx);
+    A.partial_cap = ctx->partial_cap;
+    A.flags = ctx->flags;
+    A.nact_log = ctx->prof ? ctx->bl_log : nullptr;
+    A.log_mask = ctx->bl_log_mask;
     ctx->bl_n = n;
-    H6_TRY(ctx, bl_reset(ctx), "block loop reset");
-    BlockDesc *slot[2] = {(BlockDesc *)((char *)ctx->host + kHostSlot0),
-                          (BlockDesc *)((char *)ctx->host + kHostSlot1)};
+
+    LoopDesc *slot[2] = {(LoopDesc *)((char *)ctx->host + kHostSlot0),
+                         (LoopDesc *)((char *)ctx->host + kHostSlot1)};
+    H6_TRY(ctx, bl_setup(ctx, A), "block loop set-up");
+    H6_TRY(ctx,
+           hipMemcpyAsync(slot[0], ctx->bl_desc, sizeof(LoopDesc), hipMemcpyDeviceToHost,
+                          ctx->stream),
+           "block plan readback");
+    H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    if (slot[0]->invalid) return run_blocks_host(ctx, st, n, pred, f, active, prm, t_end, stats);
     int64_t seq = 0;
     int cur = 0;
     bool have_prev = false;
+    bool done = slot[0]->done != 0;
     int batch = 4;
-    for (;;) {
+    while (!done) {
         for (int b = 0; b < batch; ++b, ++seq)
-            H6_TRY(ctx, bl_enqueue_block(ctx, st, (int)n, pred, f, active, prm, t_end, seq),
-                   "block step");
+            H6_TRY(ctx, bl_enqueue_block(ctx, A, prm->precision, seq), "block step");
+        // plan of the block after the batch: done once nothing is due before t_end
         H6_TRY(ctx,
-               hipMemcpyAsync(slot[cur], ctx->bl_desc, sizeof(BlockDesc), hipMemcpyDeviceToHost,
-                              ctx->stream),
+               hipMemcpyAsync(slot[cur], ctx->bl_desc + (seq & 1), sizeof(LoopDesc),
+                              hipMemcpyDeviceToHost, ctx->stream),
                "block status readback");
         H6_TRY(ctx, hipEventRecord(ctx->bl_ev[cur], ctx->stream), "event record");
         if (have_prev) {
@@ -500,7 +559,8 @@ static int run_blocks_device(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred 
         }
     }
     H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
-    const BlockDesc d = *slot[cur];  // the copy enqueued last
+    // the copy enqueued last (or the set-up plan when nothing was due)
+    const LoopDesc &d = have_prev ? *slot[cur] : *slot[0];
     if (!ctx->pending.empty()) H6_TRY(ctx, prof_resolve(ctx), "profile events");
     if (stats) {
         stats->blocks = d.blocks;

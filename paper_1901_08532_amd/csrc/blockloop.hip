@@ -1,22 +1,40 @@
-// Device-resident block stepping: the kernels of one block step read the
-// block time and active count from device memory, so the host enqueues
-// blocks back to back and synchronises once per batch of blocks instead of
-// once per block (the paper's code synchronises host and device every
-// step, Sec. 3 item 3; at block-step granularity that round trip would
-// cost more than the small blocks' arithmetic).
+// Device-resident block stepping (block time steps, Sec. 2.2; host-device
+// synchronisation per step, Sec. 3 item 3).
 //
-// Per block, in stream order:
-//   k_bl_select     chunk minima and tie counts of t + dt; the last
-//                   workgroup publishes t_next, n_act and the evaluation's
-//                   launch shape in a BlockDesc (n_act = 0 once t_next would
-//                   pass t_end: the block and all later ones become no-ops)
-//   k_bl_compact_predict  every particle predicted to t_next, and the
-//                   active list in index order
-//   k_bl_eval       fixed grid; each workgroup takes its (target group,
-//                   source slice) units from the BlockDesc
-//   k_bl_reduce_correct  compensated slice sums, then the corrector and
-//                   step rule for each active particle
-// The arithmetic is that of the host-sequenced path (shared bodies).
+// Particles are kept in per-level lists (level L: step 2^-L). With
+// power-of-two steps, every particle's time is the largest multiple of its
+// own step not after the current block time t, so
+//   t_next = min over occupied levels L of the next multiple of 2^-L after t,
+// and the particles due at t_next are exactly those on the levels whose step
+// divides t_next. Choosing a block is O(levels) work and its active set is a
+// concatenation of whole lists: no pass over all particles per block.
+//
+// Lists: two buffers per level, capacity n each. During a block the active
+// levels' lists are read (targets) from one buffer while the corrected
+// particles are written, by new level, into the other; a particle whose step
+// doubles (to level L0 - 1, not active) is appended to that level's current
+// list. The plan of the next block flips the buffers of the active levels.
+// List order is not significant: a target's sums do not depend on which
+// targets share its group.
+//
+// Per block, three kernels in stream order:
+//   k_bl_predict  tile kind (large active sets) only: every particle
+//                 predicted to t_next into the predicted arrays.
+//   k_bl_eval     fixed grid; each workgroup takes (target group, source
+//                 slice) units and writes slice sums. Small active sets
+//                 predict their sources and targets on the fly from the state
+//                 (a pass over all particles would cost more than their
+//                 evaluation); the tile kind reads the predicted arrays.
+//   k_bl_finish   compensated slice sums, corrector in place, list updates;
+//                 the last workgroup plans the next block.
+// Only the finishing workgroups (at most kFinGrid, fewer for small sets)
+// synchronise through device-scope atomics: on this GPU such fences and
+// atomics serialise across the device, so per-block atomics stay few.
+// Descriptors are double-buffered by block parity: block b reads desc[b & 1]
+// and its plan for b + 1 goes to desc[(b + 1) & 1], so no kernel of block b
+// sees its own descriptor change.
+#include <hip/hip_ext.h>
+
 #include "eval_body.h"
 #include "eval_mixed_body.h"
 #include "steps_body.h"
@@ -28,367 +46,614 @@ using namespace evalbody;
 using namespace mixedbody;
 using namespace stepbody;
 
-constexpr int kSelThreads = 256;
-constexpr int kSelChunk = 1024;  // particles per workgroup in select/compact
 constexpr int kSmall1Max = 16;   // active sets up to this size: one target per wave
-constexpr int kSmall2Max = 128;  // up to this size: source-parallel, two targets per wave
-constexpr int kTileBlock = 64;   // tile kernel: one wave, two targets per lane
+constexpr int kTileBlock = 64;   // tile kind: one wave, two targets per lane
 constexpr int kTileIpl = 2;
-constexpr int kWaveReduce = 24;  // slices from which one wave reduces one target
+constexpr int kWaveReduce = 24;  // slices from which waves reduce (target, component) jobs
+constexpr int kFinThreads = 512;
+constexpr int kFinGrid = 128;    // finishing workgroups at most
+constexpr int kScanThreads = 256;
 
 __device__ __forceinline__ int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
-// Exclusive prefix sum over the 256 threads of a workgroup; *total gets
-// the sum. Wave scans by shuffles, then the four wave totals.
-__device__ __forceinline__ int block_excl_scan(int v, int *total) {
-    __shared__ int wsum[kSelThreads / 64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int inc = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int o = __shfl_up(inc, off, 64);
-        if (lane >= off) inc += o;
-    }
-    if (lane == 63) wsum[w] = inc;
-    __syncthreads();
-    int before = 0, all = 0;
-#pragma unroll
-    for (int q = 0; q < kSelThreads / 64; ++q) {
-        before += q < w ? wsum[q] : 0;
-        all += wsum[q];
-    }
-    __syncthreads();
-    *total = all;
-    return before + inc - v;
+template <typename T>
+__device__ __forceinline__ T load_agent(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void store_agent(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned add_agent(unsigned *p, unsigned v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ int64_t block_min(int64_t v) {
-    __shared__ int64_t wmin[kSelThreads / 64];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const int64_t o = __shfl_xor(v, off, 64);
-        v = o < v ? o : v;
-    }
-    if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = v;
-    __syncthreads();
-    int64_t r = wmin[0];
-#pragma unroll
-    for (int q = 1; q < kSelThreads / 64; ++q) r = wmin[q] < r ? wmin[q] : r;
-    __syncthreads();
-    return r;
-}
-
-__device__ __forceinline__ int block_sum(int v) {
-    int total;
-    (void)block_excl_scan(v, &total);
-    return total;
-}
-
-__device__ __forceinline__ bool last_workgroup(unsigned *counter, unsigned nblocks) {
+// Whether this workgroup is the last of `total` to arrive at `counter`
+// (release of this workgroup's stores before, acquire of the others' after);
+// the last one resets the counter. Every thread must call it.
+__device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned total) {
     __shared__ bool is_last;
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
         const unsigned prev =
             __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        is_last = (prev == nblocks - 1);
-        if (is_last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        is_last = (prev == total - 1);
+        if (is_last) store_agent(counter, 0u);
     }
     __syncthreads();
     if (is_last) __threadfence();
     return is_last;
 }
 
-template <typename T>
-__device__ __forceinline__ T load_agent(const T *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ int32_t *level_list(const LoopArgs &A, int buf, int L) {
+    return A.lists + ((int64_t)buf * A.nl + (L - A.lev_lo)) * (int64_t)A.n;
 }
 
-// Launch shape of the evaluation for n_act targets (written into the
-// BlockDesc). Source-parallel kinds (1: one target per wave, 3: two): slices
-// of at least 256 sources (4 per lane), at most eval_grid waves in all.
-// Tile kind 0 (128 targets per one-wave workgroup): the largest slice
-// count whose units fit one round of resident workgroups (eval_grid), at
-// least four 64-source tiles per slice. Bounded by the partial capacity.
-__device__ void launch_shape(BlockDesc &d, int n, int n_act, int eval_grid, int64_t partial_cap) {
-    int split;
+// The active levels' rank offsets and list buffers of a block, copied into
+// LDS by every workgroup that maps ranks to particles.
+struct RankTable {
+    int L0, hi;
+    unsigned long long sel;
+    int off[kLevels];
+};
+
+__device__ __forceinline__ void load_rank_table(RankTable *rt, const LoopDesc *__restrict__ d) {
+    for (int L = threadIdx.x; L < kLevels; L += blockDim.x) rt->off[L] = d->off[L];
+    if (threadIdx.x == 0) {
+        rt->L0 = d->L0;
+        rt->hi = d->lv_hi;
+        rt->sel = d->sel;
+    }
+    __syncthreads();
+}
+
+// Particle of active rank k: ranks run over the active levels from the
+// highest down, level L holding ranks [off[L], off[L] + cnt[L]).
+// Out-of-range indices (which the list bookkeeping never produces) are
+// clamped and reported through the status flags instead of being used.
+__device__ __forceinline__ int rank_to_particle(const LoopArgs &A, const RankTable *rt, int k) {
+    int L = rt->L0;
+    const int hi = rt->hi;
+    while (L < hi && k < rt->off[L]) ++L;
+    const int buf = (int)((rt->sel >> L) & 1ull);
+    const int pos = k - rt->off[L];
+    const bool pos_ok = pos >= 0 && pos < A.n && L >= A.lev_lo && L < A.lev_lo + A.nl;
+    int id = level_list(A, pos_ok ? buf : 0, pos_ok ? L : A.lev_lo)[pos_ok ? pos : 0];
+    if (!pos_ok || (unsigned)id >= (unsigned)A.n) {
+        atomicOr(A.flags, kFlagLoop);
+        id = 0;
+    }
+    return id;
+}
+
+// Source/target policies of the evaluation bodies; targets through the
+// level lists. StateSrc predicts from the state to t_next on the fly,
+// ListPredSrc reads the predicted arrays.
+struct StateSrc {
+    LoopArgs A;
+    const RankTable *rt;
+    int64_t t_next;
+    __device__ __forceinline__ int target(int k) const { return rank_to_particle(A, rt, k); }
+    template <int ORDER>
+    __device__ __forceinline__ void get(int p, double *x, double *v, double *a, double *j) const {
+        static_assert(ORDER == 2, "block steps evaluate a, j, s");
+        predict_vals(A.st, p, (double)(t_next - A.st.t[p]) * kTick, x, v, a);
+        j[0] = j[1] = j[2] = 0.0;
+    }
+    __device__ __forceinline__ double mass(int p) const { return A.st.m[p]; }
+};
+
+struct ListPredSrc {
+    LoopArgs A;
+    const RankTable *rt;
+    __device__ __forceinline__ int target(int k) const { return rank_to_particle(A, rt, k); }
+    template <int ORDER>
+    __device__ __forceinline__ void get(int p, double *x, double *v, double *a, double *j) const {
+        static_assert(ORDER == 2, "block steps evaluate a, j, s");
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            x[c] = A.pred.x[c][p];
+            v[c] = A.pred.v[c][p];
+            a[c] = A.pred.a[c][p];
+            j[c] = 0.0;
+        }
+    }
+    __device__ __forceinline__ double mass(int p) const { return A.st.m[p]; }
+};
+
+// Evaluation shape for n_act targets. Source-parallel kinds (1: one target
+// per wave, 3: two): slices of at least 256 sources (4 per lane), at most
+// eval_grid waves in all. Tile kind 0 (128 targets per one-wave workgroup):
+// the largest slice count whose units fit one round of resident workgroups,
+// at least four 64-source tiles per slice. Bounded by the partial capacity.
+__device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, int64_t partial_cap) {
+    int split, kind, groups;
     if (n_act <= kSmall2Max) {
-        d.kind = n_act <= kSmall1Max ? 1 : 3;
-        d.groups = d.kind == 1 ? n_act : cdiv(n_act, 2);
+        kind = n_act <= kSmall1Max ? 1 : 3;
+        groups = kind == 1 ? n_act : cdiv(n_act, 2);
         split = cdiv(n, 256);
-        const int fit = eval_grid / d.groups;
+        const int fit = eval_grid / groups;
         split = split < fit ? split : fit;
     } else {
-        d.kind = 0;
-        d.groups = cdiv(n_act, kTileBlock * kTileIpl);
-        split = eval_grid / d.groups;
+        kind = 0;
+        groups = cdiv(n_act, kTileBlock * kTileIpl);
+        split = eval_grid / groups;
         const int cap = n / (4 * kTileBlock);
         split = split < cap ? split : cap;
     }
     const int64_t pc = partial_cap / ((int64_t)9 * n_act);
     if (split > pc) split = (int)pc;
     if (split < 1) split = 1;
-    int slice = cdiv(cdiv(n, split), 64) * 64;
-    d.slice_len = slice;
-    d.split = cdiv(n, slice);
+    const int slice = cdiv(cdiv(n, split), 64) * 64;
+    d->kind = kind;
+    d->groups = groups;
+    d->slice_len = slice;
+    d->split = cdiv(n, slice);
 }
 
-__global__ __launch_bounds__(kSelThreads) void k_bl_select(
-    const int64_t *__restrict__ t, const int64_t *__restrict__ dt, int n, int64_t t_end,
-    int64_t *chunk_min, int32_t *chunk_cnt, int32_t *chunk_off, unsigned *counter, BlockDesc *desc,
-    int32_t *nact_log, int log_mask, int64_t seq, int eval_grid, int64_t partial_cap) {
-    const int base = blockIdx.x * kSelChunk;
-    const int end = min(n, base + kSelChunk);
-    int64_t v = INT64_MAX;
-    for (int i = base + threadIdx.x; i < end; i += kSelThreads) {
-        const int64_t due = t[i] + dt[i];
-        v = due < v ? due : v;
-    }
-    const int64_t cmin = block_min(v);
-    int cnt = 0;
-    for (int i = base + threadIdx.x; i < end; i += kSelThreads) cnt += (t[i] + dt[i] == cmin);
-    cnt = block_sum(cnt);
-    if (threadIdx.x == 0) {
-        chunk_min[blockIdx.x] = cmin;
-        chunk_cnt[blockIdx.x] = cnt;
-    }
-    if (!last_workgroup(counter, gridDim.x)) return;
-    const int nb = gridDim.x;
-    int64_t r = INT64_MAX;
-    for (int b = threadIdx.x; b < nb; b += kSelThreads) {
-        const int64_t x = load_agent(&chunk_min[b]);
-        r = x < r ? x : r;
-    }
-    r = block_min(r);
-    // offsets of the chunks holding t_next: each thread scans a run of chunks
-    const int per = cdiv(nb, kSelThreads);
-    const int b0 = threadIdx.x * per;
-    int mine = 0;
-    for (int b = b0; b < b0 + per && b < nb; ++b)
-        mine += load_agent(&chunk_min[b]) == r ? load_agent(&chunk_cnt[b]) : 0;
-    int total;
-    int run = block_excl_scan(mine, &total);
-    for (int b = b0; b < b0 + per && b < nb; ++b) {
-        const bool has = load_agent(&chunk_min[b]) == r;
-        chunk_off[b] = has ? run : -1;
-        run += has ? load_agent(&chunk_cnt[b]) : 0;
-    }
-    if (threadIdx.x == 0) {
-        BlockDesc d = *desc;
-        const bool past = r > t_end;
-        d.t_next = r;
-        d.n_act = past ? 0 : total;
-        d.done = past ? 1 : 0;
-        if (!past) {
-            launch_shape(d, n, total, eval_grid, partial_cap);
-            d.blocks += 1;
-            d.particle_steps += total;
+// Targets per finishing workgroup round (many slices: one wave per target;
+// few: one thread per target) and the number of finishing workgroups with
+// work, for a block of n_act targets in `split` slices.
+__device__ __forceinline__ int fin_per_round(int split) {
+    return split >= kWaveReduce ? kFinThreads / 64 : kFinThreads;
+}
+__device__ __forceinline__ int fin_workers(int n_act, int split) {
+    const int w = cdiv(n_act, fin_per_round(split));
+    return w < kFinGrid ? w : kFinGrid;
+}
+
+// Plans the block after time t_cur into *d from the level counts cnt (in
+// LDS; d->cnt is written by the caller), with blocks / particle_steps the
+// totals so far: next block time, active levels and count, rank offsets,
+// evaluation shape; n_act = 0 and done = 1 once t_next would pass t_end.
+// One thread; reads only LDS and writes d.
+__device__ void plan_block(const LoopArgs &A, LoopDesc *d, const int *cnt, int64_t t_cur,
+                           uint64_t sel, int64_t blocks, int64_t psteps, int64_t seq_next) {
+    int64_t tn = INT64_MAX;
+    int lv_hi = -1;
+    for (int L = A.lev_lo; L < A.lev_lo + A.nl; ++L) {
+        if (cnt[L] > 0) {
+            const int64_t dtl = (int64_t)1 << (kTickBits - L);
+            const int64_t cand = (t_cur / dtl + 1) * dtl;
+            tn = cand < tn ? cand : tn;
+            lv_hi = L;
         }
-        if (nact_log) nact_log[seq & log_mask] = d.n_act;
-        *desc = d;
+    }
+    d->t_next = tn;
+    d->lv_hi = lv_hi;
+    d->sel = sel;
+    d->invalid = 0;
+    int n_act = 0;
+    if (lv_hi < 0 || tn > A.t_end) {
+        d->done = 1;
+        d->L0 = lv_hi;
+    } else {
+        int L0 = kTickBits - __builtin_ctzll((unsigned long long)tn);
+        if (L0 < A.lev_lo) L0 = A.lev_lo;
+        for (int L = lv_hi; L >= L0; --L) {
+            d->off[L] = n_act;
+            n_act += cnt[L];
+        }
+        d->L0 = L0;
+        d->done = 0;
+        launch_shape(d, A.n, n_act, A.eval_grid, A.partial_cap);
+        blocks += 1;
+        psteps += n_act;
+    }
+    d->blocks = blocks;
+    d->particle_steps = psteps;
+    d->n_act = n_act;
+    if (A.nact_log) A.nact_log[seq_next & A.log_mask] = n_act;
+}
+
+// List slots handed out in a block: the sizes of the rebuilt lists of the
+// active levels and the count appended to level L0 - 1. Kept in LDS when a
+// single workgroup finishes the block, in LoopScratch otherwise.
+struct Tally {
+    unsigned reb[kLevels];
+    unsigned app;
+};
+
+// Level counts after block `cur` (cur_cnt: its counts, in LDS; the rebuilt
+// lists of the active levels; the appended particles of level L0 - 1), then
+// the plan of the next block into *dn. The whole workgroup, after every list
+// update of the block: one thread per level gathers, one thread plans from
+// LDS. solo: the tallies are this workgroup's (LDS), else the device's.
+__device__ void plan_next(const LoopArgs &A, const LoopDesc *__restrict__ cur, const int *cur_cnt,
+                          const Tally *solo, LoopDesc *dn, int64_t seq) {
+    __shared__ int s_cnt[kLevels];
+    LoopScratch *scr = A.scr;
+    const int L0 = cur->L0;
+    for (int L = threadIdx.x; L < kLevels; L += blockDim.x) {
+        int c = cur_cnt[L];
+        if (L >= A.lev_lo && L < A.lev_lo + A.nl) {
+            if (L >= L0) {
+                if (solo) {
+                    c = (int)solo->reb[L];
+                } else {
+                    c = (int)load_agent(&scr->reb[L]);
+                    store_agent(&scr->reb[L], 0u);
+                }
+            } else if (L == L0 - 1) {
+                if (solo) {
+                    c += (int)solo->app;
+                } else {
+                    c += (int)load_agent(&scr->app);
+                    store_agent(&scr->app, 0u);
+                }
+            }
+        }
+        s_cnt[L] = c;
+        dn->cnt[L] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t flip = 0;
+        for (int L = L0 > A.lev_lo ? L0 : A.lev_lo; L < A.lev_lo + A.nl; ++L) flip |= 1ull << L;
+        plan_block(A, dn, s_cnt, cur->t_next, cur->sel ^ flip, cur->blocks, cur->particle_steps,
+                   seq + 1);
     }
 }
 
-// Predicts every particle of the chunk to t_next, and writes the chunk's
-// due particles, in index order, at the chunk's offset in the active list.
-__global__ __launch_bounds__(kSelThreads) void k_bl_compact_predict(h6_state st, int n,
-                                                                    const BlockDesc *desc,
-                                                                    const int32_t *chunk_off,
-                                                                    int32_t *active, h6_pred out) {
-    __shared__ int wcnt[kSelThreads / 64];
-    if (desc->n_act == 0) return;
-    const int64_t tn = desc->t_next;
-    const int base = blockIdx.x * kSelChunk;
-    const int end = min(n, base + kSelChunk);
-    for (int i = base + threadIdx.x; i < end; i += kSelThreads)
-        predict_one(st, i, (double)(tn - st.t[i]) * kTick, out);
-    const int off0 = chunk_off[blockIdx.x];
-    if (off0 < 0) return;  // no particle of this chunk is due
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int run = off0;
-    for (int r = base; r < end; r += kSelThreads) {
-        const int i = r + threadIdx.x;
-        const bool due = i < end && (st.t[i] + st.dt[i] == tn);
-        const unsigned long long mask = __ballot(due);
-        const int before = __popcll(mask & ((1ull << lane) - 1ull));
-        if (lane == 0) wcnt[w] = __popcll(mask);
-        __syncthreads();
-        int woff = 0, tot = 0;
-#pragma unroll
-        for (int q = 0; q < kSelThreads / 64; ++q) {
-            woff += q < w ? wcnt[q] : 0;
-            tot += wcnt[q];
-        }
-        if (due) active[run + woff + before] = i;
-        run += tot;
-        __syncthreads();
-    }
+__global__ __launch_bounds__(256) void k_bl_predict(LoopArgs A, int64_t seq) {
+    const LoopDesc *__restrict__ d = A.desc + (seq & 1);
+    if (d->n_act == 0 || d->kind != 0) return;
+    const int64_t tn = d->t_next;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += gridDim.x * blockDim.x)
+        predict_one(A.st, i, (double)(tn - A.st.t[i]) * kTick, A.pred);
 }
 
 template <bool MIXED, bool SKIPSELF>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_bl_eval(
-    SrcPtrs src, const int32_t *__restrict__ active, int n, double eps2, const BlockDesc *desc,
-    double *partial, OutPtrs force) {
-    const int n_act = desc->n_act;
+    LoopArgs A, int64_t seq) {
+    const LoopDesc *__restrict__ d = A.desc + (seq & 1);
+    const int n_act = d->n_act;
     if (n_act == 0) return;
-    const int split = desc->split, slice_len = desc->slice_len, groups = desc->groups;
-    const int kind = desc->kind;
+    const int split = d->split, slice_len = d->slice_len, groups = d->groups;
+    const int kind = d->kind;
     OutPtrs out;
-    int64_t slice_stride = 0;
-    if (split == 1) {
-        out = force;
-    } else {
 #pragma unroll
-        for (int c = 0; c < kMaxOut; ++c) out.p[c] = c < 9 ? partial + (int64_t)c * n_act : nullptr;
-        slice_stride = (int64_t)9 * n_act;
-    }
+    for (int c = 0; c < kMaxOut; ++c) out.p[c] = c < 9 ? A.partial + (int64_t)c * n_act : nullptr;
+    const int64_t slice_stride = (int64_t)9 * n_act;
     const int units = groups * split;
+    if ((int)blockIdx.x >= units) return;
+    __shared__ RankTable rt;
+    load_rank_table(&rt, d);
+    if (kind == 0) {
+        const ListPredSrc S{A, &rt};
+        for (int u = blockIdx.x; u < units; u += gridDim.x) {
+            const int g = u / split, sl = u - g * split;
+            if constexpr (MIXED)
+                mixed_tile_body<kTileBlock, kTileIpl, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len,
+                                                                out, slice_stride, g, sl);
+            else
+                eval_tile_body<2, kTileBlock, kTileIpl, SKIPSELF>(S, A.n, n_act, A.eps2,
+                                                                  slice_len, out, slice_stride, g,
+                                                                  sl);
+        }
+        return;
+    }
+    const StateSrc S{A, &rt, d->t_next};
     for (int u = blockIdx.x; u < units; u += gridDim.x) {
         const int g = u / split, sl = u - g * split;
         if (kind == 1) {
             if constexpr (MIXED)
-                mixed_small_body<1, SKIPSELF>(src, active, n, n_act, eps2, slice_len, out,
-                                              slice_stride, g, sl);
+                mixed_small_body<1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, out, slice_stride,
+                                              g, sl);
             else
-                eval_small_body<1, SKIPSELF>(src, active, n, n_act, eps2, slice_len, out,
-                                             slice_stride, g, sl);
-        } else if (kind == 3) {
-            if constexpr (MIXED)
-                mixed_small_body<2, SKIPSELF>(src, active, n, n_act, eps2, slice_len, out,
-                                              slice_stride, g, sl);
-            else
-                eval_small_body<2, SKIPSELF>(src, active, n, n_act, eps2, slice_len, out,
-                                             slice_stride, g, sl);
+                eval_small_body<1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, out, slice_stride,
+                                             g, sl);
         } else {
             if constexpr (MIXED)
-                mixed_tile_body<kTileBlock, kTileIpl, SKIPSELF>(src, active, n, n_act, eps2,
-                                                                slice_len, out, slice_stride, g, sl);
+                mixed_small_body<2, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, out, slice_stride,
+                                              g, sl);
             else
-                eval_tile_body<2, kTileBlock, kTileIpl, SKIPSELF>(src, active, n, n_act, eps2,
-                                                                  slice_len, out, slice_stride, g,
-                                                                  sl);
+                eval_small_body<2, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, out, slice_stride,
+                                             g, sl);
         }
     }
 }
 
-__device__ __forceinline__ void neumaier(double &s, double &c, double x) {
+// Workgroup-aggregated list insertion: one slot reservation per level per
+// workgroup round, from the device counters, or from this workgroup's own
+// tally (solo) when it finishes the block alone. cur_cnt: the block's
+// level counts (LDS). Every thread calls it; valid marks the threads with a
+// particle. Ends with a barrier.
+__device__ void list_insert_wg(const LoopArgs &A, const RankTable *rt, const int *cur_cnt,
+                               Tally *solo, bool valid, int id, int lev) {
+    __shared__ unsigned lcount[kLevels];
+    __shared__ unsigned lbase[kLevels];
+    for (int L = threadIdx.x; L < kLevels; L += blockDim.x) lcount[L] = 0u;
+    __syncthreads();
+    unsigned rank = 0;
+    if (valid) rank = atomicAdd(&lcount[lev], 1u);
+    __syncthreads();
+    const int L0 = rt->L0;
+    for (int L = threadIdx.x; L < kLevels; L += blockDim.x) {
+        const unsigned c = lcount[L];
+        if (c > 0) {
+            if (solo) {
+                if (L >= L0) {
+                    lbase[L] = solo->reb[L];
+                    solo->reb[L] += c;
+                } else {
+                    lbase[L] = (unsigned)cur_cnt[L] + solo->app;
+                    solo->app += c;
+                }
+            } else {
+                lbase[L] = L >= L0 ? add_agent(&A.scr->reb[L], c)
+                                   : (unsigned)cur_cnt[L] + add_agent(&A.scr->app, c);
+            }
+        }
+    }
+    __syncthreads();
+    if (valid) {
+        const int buf = (int)((rt->sel >> lev) & 1ull) ^ (lev >= L0 ? 1 : 0);
+        const unsigned slot = lbase[lev] + rank;
+        if (slot < (unsigned)A.n && lev >= A.lev_lo && lev < A.lev_lo + A.nl)
+            level_list(A, buf, lev)[slot] = id;
+        else
+            atomicOr(A.flags, kFlagLoop);
+    }
+    __syncthreads();
+}
+
+// Neumaier step: s + comp += x.
+__device__ __forceinline__ void neumaier(double &s, double &comp, double x) {
     const double t = s + x;
-    c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+    comp += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
     s = t;
 }
 
-// Slice sums (if any) and the corrector for every active particle. Few
-// slices: one thread per target, sums in slice order; many slices: one
-// wave per target, lanes over slices, fixed butterfly. The reduced forces
-// are also stored in `force` (active order).
-__global__ __launch_bounds__(256) void k_bl_reduce_correct(h6_state st,
-                                                           const int32_t *__restrict__ active,
-                                                           const BlockDesc *desc,
-                                                           const double *__restrict__ partial,
-                                                           OutPtrs force, double eta6, int lev_min,
-                                                           int lev_max, int32_t *flags) {
-    const int n_act = desc->n_act;
-    if (n_act == 0) return;
-    const int split = desc->split;
-    const int64_t tn = desc->t_next;
-    if (split < kWaveReduce) {
-        for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_act;
-             k += gridDim.x * blockDim.x) {
-            double f[9];
-            if (split == 1) {
-#pragma unroll
-                for (int c = 0; c < 9; ++c) f[c] = force.p[c][k];
-            } else {
-#pragma unroll
-                for (int c = 0; c < 9; ++c) {
-                    double s = 0.0, comp = 0.0;
-                    for (int sl = 0; sl < split; ++sl)
-                        neumaier(s, comp, partial[((int64_t)sl * 9 + c) * n_act + k]);
-                    f[c] = s + comp;
-                    force.p[c][k] = f[c];
-                }
-            }
-            correct_one<false>(st, active[k], f, f + 3, f + 6, tn, 0.0, eta6, lev_min, lev_max,
-                               flags);
+__global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t seq) {
+    const LoopDesc *__restrict__ d = A.desc + (seq & 1);
+    LoopDesc *dn = A.desc + ((seq + 1) & 1);
+    const int n_act = d->n_act;
+    if (n_act == 0) {
+        // nothing due before t_end: carry the final descriptor forward
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            *dn = *d;
+            if (A.nact_log) A.nact_log[(seq + 1) & A.log_mask] = 0;
         }
         return;
     }
-    const int lane = threadIdx.x & 63;
-    const int waves = gridDim.x * (blockDim.x >> 6);
-    for (int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); k < n_act; k += waves) {
-        double f[9];
+    const int split = d->split;
+    const int per = fin_per_round(split);
+    const int workers = fin_workers(n_act, split);
+    if ((int)blockIdx.x >= workers) return;
+    const int64_t tn = d->t_next;
+    const bool solo = workers == 1;  // no other workgroup: tallies in LDS, no device atomics
+    __shared__ double fs[kFinThreads * 9];
+    __shared__ RankTable rt;
+    __shared__ int cur_cnt[kLevels];
+    __shared__ Tally tally;
+    for (int L = threadIdx.x; L < kLevels; L += blockDim.x) {
+        cur_cnt[L] = d->cnt[L];
+        tally.reb[L] = 0u;
+    }
+    if (threadIdx.x == 0) tally.app = 0u;
+    load_rank_table(&rt, d);  // ends with a barrier
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int k0 = blockIdx.x * per; k0 < n_act; k0 += workers * per) {
+        const int nt = n_act - k0 < per ? n_act - k0 : per;
+        const bool valid = tid < nt;
+        int id = 0, lev = 0;
+        if (valid) id = rank_to_particle(A, &rt, k0 + tid);  // overlaps the slice loads
+        const double *__restrict__ part = A.partial;
+        if (split >= kWaveReduce) {
+            // one wave per target: lanes over slices, the nine components'
+            // loads of four slices per lane issued together, then a fixed
+            // butterfly each
+            if (w < nt) {
+                const int64_t k = k0 + w;
+                double s[9], comp[9];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) {
-            double s = 0.0, comp = 0.0;
-            for (int sl = lane; sl < split; sl += 64)
-                neumaier(s, comp, partial[((int64_t)sl * 9 + c) * n_act + k]);
-            wave_comp_sum(s, comp);
-            f[c] = s + comp;
-        }
-        if (lane == 0) {
+                for (int c = 0; c < 9; ++c) s[c] = comp[c] = 0.0;
+                for (int sl0 = 0; sl0 < split; sl0 += 256) {
+                    double x[4][9];
 #pragma unroll
-            for (int c = 0; c < 9; ++c) force.p[c][k] = f[c];
-            correct_one<false>(st, active[k], f, f + 3, f + 6, tn, 0.0, eta6, lev_min, lev_max,
-                               flags);
+                    for (int q = 0; q < 4; ++q) {
+                        const int sl = sl0 + q * 64 + lane;
+#pragma unroll
+                        for (int c = 0; c < 9; ++c)
+                            x[q][c] = sl < split ? part[((int64_t)sl * 9 + c) * n_act + k] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int c = 0; c < 9; ++c) neumaier(s[c], comp[c], x[q][c]);
+                }
+#pragma unroll
+                for (int c = 0; c < 9; ++c) {
+                    wave_comp_sum(s[c], comp[c]);
+                    if (lane == 0) fs[w * 9 + c] = s[c] + comp[c];
+                }
+            }
+        } else if (valid) {
+            // one thread per target, slices in order, four slices' loads at once
+            const int64_t k = k0 + tid;
+            double s[9], comp[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) s[c] = comp[c] = 0.0;
+            int sl = 0;
+            for (; sl + 4 <= split; sl += 4) {
+                double x[4][9];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int c = 0; c < 9; ++c)
+                        x[q][c] = part[((int64_t)(sl + q) * 9 + c) * n_act + k];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) neumaier(s[c], comp[c], x[q][c]);
+            }
+            for (; sl < split; ++sl)
+#pragma unroll
+                for (int c = 0; c < 9; ++c)
+                    neumaier(s[c], comp[c], part[((int64_t)sl * 9 + c) * n_act + k]);
+#pragma unroll
+            for (int c = 0; c < 9; ++c) fs[tid * 9 + c] = s[c] + comp[c];
         }
+        __syncthreads();
+        if (valid) {
+            double x1[3], v1[3], c1[3], f[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) f[c] = fs[tid * 9 + c];
+            correct_vals<false>(A.st, id, f, f + 3, f + 6, tn, 0.0, A.eta6, A.lev_min,
+                                A.lev_max, A.flags, x1, v1, c1, &lev);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                A.st.x[c][id] = x1[c];
+                A.st.v[c][id] = v1[c];
+                A.st.a[c][id] = f[c];
+                A.st.j[c][id] = f[3 + c];
+                A.st.s[c][id] = f[6 + c];
+                A.st.c[c][id] = c1[c];
+            }
+            A.st.t[id] = tn;
+            A.st.dt[id] = (int64_t)1 << (kTickBits - lev);
+        }
+        list_insert_wg(A, &rt, cur_cnt, solo ? &tally : nullptr, valid, id, lev);
+        // (ends with a barrier: fs reusable)
+    }
+    if (solo) {
+        plan_next(A, d, cur_cnt, &tally, dn, seq);
+        return;
+    }
+    if (!arrive_last(&A.scr->done_fin, (unsigned)workers)) return;
+    plan_next(A, d, cur_cnt, nullptr, dn, seq);
+}
+
+// ---------------------------------------------------------------- set-up
+
+__global__ void k_bl_setup_init(LoopArgs A) {
+    LoopScratch *scr = A.scr;
+    for (int i = threadIdx.x; i < kLevels; i += blockDim.x) scr->reb[i] = 0u;
+    if (threadIdx.x == 0) {
+        scr->done_fin = scr->app = scr->bad = 0u;
+        scr->t_max = 0ull;
+        scr->due_min = ~0ull;
     }
 }
 
-__global__ void k_bl_reset(BlockDesc *desc) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        BlockDesc d = {};
-        *desc = d;
+__device__ __forceinline__ unsigned long long wg_reduce_u64(unsigned long long v, bool take_max) {
+    __shared__ unsigned long long part[kScanThreads / 64];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off, 64);
+        v = take_max ? (o > v ? o : v) : (o < v ? o : v);
     }
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    unsigned long long r = part[0];
+    for (int q = 1; q < kScanThreads / 64; ++q)
+        r = take_max ? (part[q] > r ? part[q] : r) : (part[q] < r ? part[q] : r);
+    __syncthreads();
+    return r;
+}
+
+// Checks that every particle sits on the block grid (step a power of two
+// within the run's levels, time a multiple of it), finds the latest time
+// and the earliest due time, and fills list buffer 0 by level.
+__global__ __launch_bounds__(kScanThreads) void k_bl_setup_scan(LoopArgs A) {
+    const int i = blockIdx.x * kScanThreads + threadIdx.x;
+    const bool in = i < A.n;
+    int64_t t = 0, dt = 1;
+    if (in) {
+        t = A.st.t[i];
+        dt = A.st.dt[i];
+    }
+    bool ok = dt > 0 && (dt & (dt - 1)) == 0 && dt <= ((int64_t)1 << kTickBits) && t >= 0 &&
+              t <= ((int64_t)1 << 61) && t % dt == 0;
+    const int lev = ok ? level_of_ticks(dt) : -1;
+    ok = ok && lev >= A.lev_lo && lev < A.lev_lo + A.nl;
+    const bool bad = in && !ok;
+    const unsigned nbad = (unsigned)__popcll(__ballot(bad));
+    if ((threadIdx.x & 63) == 0 && nbad) add_agent(&A.scr->bad, nbad);
+    const bool good = in && ok;
+    const unsigned long long tmax = wg_reduce_u64(good ? (unsigned long long)t : 0ull, true);
+    const unsigned long long dmin =
+        wg_reduce_u64(good ? (unsigned long long)(t + dt) : ~0ull, false);
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_max(&A.scr->t_max, tmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_min(&A.scr->due_min, dmin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // fill: buffer 0, slots from the rebuild counters
+    __shared__ unsigned lcount[kLevels];
+    __shared__ unsigned lbase[kLevels];
+    for (int L = threadIdx.x; L < kLevels; L += blockDim.x) lcount[L] = 0u;
+    __syncthreads();
+    unsigned rank = 0;
+    if (good) rank = atomicAdd(&lcount[lev], 1u);
+    __syncthreads();
+    for (int L = threadIdx.x; L < kLevels; L += blockDim.x)
+        if (lcount[L] > 0) lbase[L] = add_agent(&A.scr->reb[L], lcount[L]);
+    __syncthreads();
+    if (good) level_list(A, 0, lev)[lbase[lev] + rank] = i;
+}
+
+// Level counts from the fill, then the plan of block 0 into desc[0]; a
+// state off the block grid is reported as invalid (and done).
+__global__ void k_bl_setup_plan(LoopArgs A) {
+    __shared__ int s_cnt[kLevels];
+    LoopScratch *scr = A.scr;
+    LoopDesc *d = A.desc;
+    const unsigned long long tmax = scr->t_max, dmin = scr->due_min;
+    const bool invalid = scr->bad != 0u || dmin <= tmax;
+    for (int L = threadIdx.x; L < kLevels; L += blockDim.x) {
+        const int c = invalid ? 0 : (int)scr->reb[L];
+        s_cnt[L] = c;
+        d->cnt[L] = c;
+        scr->reb[L] = 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    scr->bad = 0u;
+    if (invalid) {
+        d->sel = 0ull;
+        d->blocks = 0;
+        d->particle_steps = 0;
+        d->invalid = 1;
+        d->n_act = 0;
+        d->done = 1;
+        d->t_next = 0;
+        if (A.nact_log) A.nact_log[0] = 0;
+        return;
+    }
+    plan_block(A, d, s_cnt, (int64_t)tmax, 0ull, 0, 0, 0);
 }
 
 }  // namespace
 
-int bl_select_blocks(int64_t n) { return (int)((n + kSelChunk - 1) / kSelChunk); }
 int bl_eval_grid(h6_ctx ctx) { return ctx->n_cu * 8; }  // one round of resident tile workgroups
 
-hipError_t bl_reset(h6_ctx ctx) {
-    hipLaunchKernelGGL(k_bl_reset, dim3(1), dim3(64), 0, ctx->stream, ctx->bl_desc);
+int64_t bl_list_ints(int64_t n, int nl) { return 2 * (int64_t)nl * n; }
+
+hipError_t bl_setup(h6_ctx ctx, const LoopArgs &A) {
+    hipLaunchKernelGGL(k_bl_setup_init, dim3(1), dim3(64), 0, ctx->stream, A);
+    hipLaunchKernelGGL(k_bl_setup_scan, dim3((A.n + kScanThreads - 1) / kScanThreads),
+                       dim3(kScanThreads), 0, ctx->stream, A);
+    hipLaunchKernelGGL(k_bl_setup_plan, dim3(1), dim3(64), 0, ctx->stream, A);
     return hipGetLastError();
 }
 
-hipError_t bl_enqueue_block(h6_ctx ctx, h6_state *st, int n, const h6_pred *pred,
-                            const h6_force *f, int32_t *active, const h6_params *prm,
-                            int64_t t_end, int64_t seq) {
-    const int nb = bl_select_blocks(n);
-    int64_t *cmin = ctx->sched64 + 2;
-    int32_t *ccnt = ctx->sched32;
-    int32_t *coff = ctx->sched32 + nb;
-    const int eval_grid = bl_eval_grid(ctx);
-    hipLaunchKernelGGL(k_bl_select, dim3(nb), dim3(kSelThreads), 0, ctx->stream, st->t, st->dt, n,
-                       t_end, cmin, ccnt, coff, ctx->counters + 3, ctx->bl_desc, ctx->bl_log,
-                       ctx->bl_log_mask, seq, eval_grid, ctx->partial_cap);
-    hipLaunchKernelGGL(k_bl_compact_predict, dim3(nb), dim3(kSelThreads), 0, ctx->stream, *st, n,
-                       (const BlockDesc *)ctx->bl_desc, (const int32_t *)coff, active, *pred);
-    SrcPtrs src;
-    for (int c = 0; c < 3; ++c) {
-        src.x[c] = pred->x[c];
-        src.v[c] = pred->v[c];
-        src.a[c] = pred->a[c];
-        src.j[c] = nullptr;
-    }
-    src.m = st->m;
-    OutPtrs fo;
-    for (int c = 0; c < kMaxOut; ++c) fo.p[c] = nullptr;
-    for (int c = 0; c < 3; ++c) {
-        fo.p[c] = f->a[c];
-        fo.p[3 + c] = f->j[c];
-        fo.p[6 + c] = f->s[c];
-    }
+hipError_t bl_enqueue_block(h6_ctx ctx, const LoopArgs &A, int precision, int64_t seq) {
+    const int pgrid = ctx->n_cu > 1 ? ctx->n_cu / 2 : 1;
+    hipLaunchKernelGGL(k_bl_predict, dim3(pgrid), dim3(256), 0, ctx->stream, A, seq);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->prof) {
-        hipError_t pe = prof_begin(ctx, &ev0, &ev1);
+        hipError_t pe = prof_events(ctx, &ev0, &ev1);
         if (pe != hipSuccess) return pe;
     }
-    const bool skip = ctx->eps2 == 0.0;
-    const bool mixed = prm->precision == H6_MIXED;
-#define H6_BL_EVAL(M, S)                                                                          \
-    hipLaunchKernelGGL((k_bl_eval<M, S>), dim3(eval_grid), dim3(64), 0, ctx->stream, src, active, \
-                       n, ctx->eps2, (const BlockDesc *)ctx->bl_desc, ctx->partial, fo)
+    const bool skip = A.eps2 == 0.0;
+    const bool mixed = precision == H6_MIXED;
+    // with the measurement hook on, the events are those of the dispatch
+    // itself (no separate marker packets in the stream)
+#define H6_BL_EVAL(M, S)                                                                         \
+    hipExtLaunchKernelGGL((k_bl_eval<M, S>), dim3(A.eval_grid), dim3(64), 0, ctx->stream, ev0, \
+                          ev1, 0u, A, seq)
     if (mixed) {
         if (skip) H6_BL_EVAL(true, true); else H6_BL_EVAL(true, false);
     } else {
@@ -398,14 +663,10 @@ hipError_t bl_enqueue_block(h6_ctx ctx, h6_state *st, int n, const h6_pred *pred
     if (ctx->prof) {
         hipError_t pe = hipGetLastError();
         if (pe != hipSuccess) return pe;
-        pe = prof_end_seq(ctx, ev0, ev1, prm->precision, seq);
+        pe = prof_push_seq(ctx, ev0, ev1, precision, seq);
         if (pe != hipSuccess) return pe;
     }
-    const double e = prm->eta, e2 = e * e;
-    hipLaunchKernelGGL(k_bl_reduce_correct, dim3(ctx->n_cu * 4), dim3(256), 0, ctx->stream, *st,
-                       (const int32_t *)active, (const BlockDesc *)ctx->bl_desc,
-                       (const double *)ctx->partial, fo, e2 * e2 * e2, prm->lev_min, prm->lev_max,
-                       ctx->flags);
+    hipLaunchKernelGGL(k_bl_finish, dim3(kFinGrid), dim3(kFinThreads), 0, ctx->stream, A, seq);
     return hipGetLastError();
 }
 

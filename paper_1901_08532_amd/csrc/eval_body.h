@@ -70,14 +70,37 @@ __device__ __forceinline__ void pair_acc2(double dx, double dy, double dz, doubl
 // Far, massless padding source: contributes exactly zero.
 constexpr double kPadPos = 1.0e18;
 
+// Where a body finds its targets and sources. Every body takes a policy
+// object with
+//   int target(int k)             particle index of target rank k
+//   void get<ORDER>(p, x, v, a, j) the (predicted) x, v, and for ORDER >= 2
+//                                 a, for ORDER 3 j, of particle p
+//   double mass(int p)
+// PredSrc reads predicted arrays and an optional active list (NULL: rank k
+// is particle k).
+struct PredSrc {
+    SrcPtrs src;
+    const int32_t *active;
+    __device__ __forceinline__ int target(int k) const { return active ? active[k] : k; }
+    template <int ORDER>
+    __device__ __forceinline__ void get(int p, double *x, double *v, double *a, double *j) const {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            x[c] = src.x[c][p];
+            v[c] = src.v[c][p];
+            a[c] = ORDER >= 2 ? src.a[c][p] : 0.0;
+            j[c] = ORDER >= 3 ? src.j[c][p] : 0.0;
+        }
+    }
+    __device__ __forceinline__ double mass(int p) const { return src.m[p]; }
+};
+
 // Body of the target-parallel LDS-tiled evaluation for the workgroup that
 // owns target block ib (BLOCK * IPL targets) and source slice sl.
-template <int ORDER, int BLOCK, int IPL, bool SKIPSELF>
-__device__ __forceinline__ void eval_tile_body(const SrcPtrs &src,
-                                               const int32_t *__restrict__ active, int n,
-                                               int n_act, double eps2, int slice_len,
-                                               const OutPtrs &out, int64_t slice_stride, int ib,
-                                               int sl) {
+template <int ORDER, int BLOCK, int IPL, bool SKIPSELF, class SRC>
+__device__ __forceinline__ void eval_tile_body(const SRC &S, int n, int n_act, double eps2,
+                                               int slice_len, const OutPtrs &out,
+                                               int64_t slice_stride, int ib, int sl) {
     using T = Traits<ORDER>;
     constexpr int NREC = T::NREC;
     constexpr int NACC = T::NACC;
@@ -92,15 +115,9 @@ __device__ __forceinline__ void eval_tile_body(const SrcPtrs &src,
         int k = (ib * IPL + u) * BLOCK + tid;
         kid[u] = k;
         int kc = k < n_act ? k : n_act - 1;
-        int p = active ? active[kc] : kc;
+        int p = S.target(kc);
         pid[u] = p;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            xi[u][c] = src.x[c][p];
-            vi[u][c] = src.v[c][p];
-            ai[u][c] = ORDER >= 2 ? src.a[c][p] : 0.0;
-            ji[u][c] = ORDER >= 3 ? src.j[c][p] : 0.0;
-        }
+        S.template get<ORDER>(p, xi[u], vi[u], ai[u], ji[u]);
     }
 
     double acc[IPL][NACC], hi[IPL][NACC], lo[IPL][NACC];
@@ -118,18 +135,20 @@ __device__ __forceinline__ void eval_tile_body(const SrcPtrs &src,
             const int jj = jt + tid;
             double2 *rec = &tile[tid * NREC];
             if (jj < je) {
-                rec[0] = make_double2(src.x[0][jj], src.x[1][jj]);
-                rec[1] = make_double2(src.x[2][jj], src.m[jj]);
-                rec[2] = make_double2(src.v[0][jj], src.v[1][jj]);
+                double xs[3], vs[3], as[3], js[3];
+                S.template get<ORDER>(jj, xs, vs, as, js);
+                rec[0] = make_double2(xs[0], xs[1]);
+                rec[1] = make_double2(xs[2], S.mass(jj));
+                rec[2] = make_double2(vs[0], vs[1]);
                 if (ORDER == 1) {
-                    rec[3] = make_double2(src.v[2][jj], 0.0);
+                    rec[3] = make_double2(vs[2], 0.0);
                 } else {
-                    rec[3] = make_double2(src.v[2][jj], src.a[0][jj]);
-                    rec[4] = make_double2(src.a[1][jj], src.a[2][jj]);
+                    rec[3] = make_double2(vs[2], as[0]);
+                    rec[4] = make_double2(as[1], as[2]);
                 }
                 if (ORDER == 3) {
-                    rec[5] = make_double2(src.j[0][jj], src.j[1][jj]);
-                    rec[6] = make_double2(src.j[2][jj], 0.0);
+                    rec[5] = make_double2(js[0], js[1]);
+                    rec[6] = make_double2(js[2], 0.0);
                 }
             } else {
                 rec[0] = make_double2(kPadPos, kPadPos);
@@ -251,12 +270,10 @@ __device__ __forceinline__ void eval_tile_body(const SrcPtrs &src,
 // a fixed butterfly. Grid: (one wave per TPW targets) x (source slices).
 constexpr int kSmallFlush = 16;
 
-template <int TPW, bool SKIPSELF>
-__device__ __forceinline__ void eval_small_body(const SrcPtrs &src,
-                                                const int32_t *__restrict__ active, int n,
-                                                int n_act, double eps2, int slice_len,
-                                                const OutPtrs &out, int64_t slice_stride,
-                                                int wave, int sl) {
+template <int TPW, bool SKIPSELF, class SRC>
+__device__ __forceinline__ void eval_small_body(const SRC &S, int n, int n_act, double eps2,
+                                                int slice_len, const OutPtrs &out,
+                                                int64_t slice_stride, int wave, int sl) {
     const int lane = threadIdx.x & 63;
     double xi[TPW][3], vi[TPW][3], ai[TPW][3];
     int pid[TPW];
@@ -264,14 +281,10 @@ __device__ __forceinline__ void eval_small_body(const SrcPtrs &src,
     for (int t = 0; t < TPW; ++t) {
         int k = wave * TPW + t;
         k = k < n_act ? k : n_act - 1;
-        const int p = active ? active[k] : k;
+        const int p = S.target(k);
         pid[t] = p;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            xi[t][c] = src.x[c][p];
-            vi[t][c] = src.v[c][p];
-            ai[t][c] = src.a[c][p];
-        }
+        double jd[3];
+        S.template get<2>(p, xi[t], vi[t], ai[t], jd);
     }
     double acc[TPW][9], hi[TPW][9], lo[TPW][9];
 #pragma unroll
@@ -283,10 +296,12 @@ __device__ __forceinline__ void eval_small_body(const SrcPtrs &src,
     const int je = min(n, jb + slice_len);
     int since_flush = 0;
     for (int j = jb + lane; j < je; j += 64) {
-        const double xj0 = src.x[0][j], xj1 = src.x[1][j], xj2 = src.x[2][j];
-        const double vj0 = src.v[0][j], vj1 = src.v[1][j], vj2 = src.v[2][j];
-        const double aj0 = src.a[0][j], aj1 = src.a[1][j], aj2 = src.a[2][j];
-        const double mj = src.m[j];
+        double xs[3], vs[3], as[3], jd[3];
+        S.template get<2>(j, xs, vs, as, jd);
+        const double xj0 = xs[0], xj1 = xs[1], xj2 = xs[2];
+        const double vj0 = vs[0], vj1 = vs[1], vj2 = vs[2];
+        const double aj0 = as[0], aj1 = as[1], aj2 = as[2];
+        const double mj = S.mass(j);
 #pragma unroll
         for (int t = 0; t < TPW; ++t) {
             const double dx = xj0 - xi[t][0], dy = xj1 - xi[t][1], dz = xj2 - xi[t][2];
@@ -323,6 +338,27 @@ __device__ __forceinline__ void eval_small_body(const SrcPtrs &src,
             if (lane == 0 && k < n_act) out.p[q][soff + k] = sv + cv;
         }
     }
+}
+
+// The bodies over predicted arrays (the host-shaped launches).
+template <int ORDER, int BLOCK, int IPL, bool SKIPSELF>
+__device__ __forceinline__ void eval_tile_body(const SrcPtrs &src,
+                                               const int32_t *__restrict__ active, int n,
+                                               int n_act, double eps2, int slice_len,
+                                               const OutPtrs &out, int64_t slice_stride, int ib,
+                                               int sl) {
+    eval_tile_body<ORDER, BLOCK, IPL, SKIPSELF>(PredSrc{src, active}, n, n_act, eps2, slice_len,
+                                                out, slice_stride, ib, sl);
+}
+
+template <int TPW, bool SKIPSELF>
+__device__ __forceinline__ void eval_small_body(const SrcPtrs &src,
+                                                const int32_t *__restrict__ active, int n,
+                                                int n_act, double eps2, int slice_len,
+                                                const OutPtrs &out, int64_t slice_stride,
+                                                int wave, int sl) {
+    eval_small_body<TPW, SKIPSELF>(PredSrc{src, active}, n, n_act, eps2, slice_len, out,
+                                   slice_stride, wave, sl);
 }
 
 }  // namespace evalbody

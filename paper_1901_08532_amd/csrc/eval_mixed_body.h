@@ -4,6 +4,7 @@
 #pragma once
 
 #include "device_math.h"
+#include "eval_body.h"
 #include "h6_internal.h"
 
 namespace h6 {
@@ -58,12 +59,10 @@ struct alignas(16) RecMixed {
 };
 
 // Body for the workgroup owning target block ib and source slice sl.
-template <int BLOCK, int IPL, bool SKIPSELF>
-__device__ __forceinline__ void mixed_tile_body(const SrcPtrs &src,
-                                                const int32_t *__restrict__ active, int n,
-                                                int n_act, double eps2, int slice_len,
-                                                const OutPtrs &out, int64_t slice_stride, int ib,
-                                                int sl) {
+template <int BLOCK, int IPL, bool SKIPSELF, class SRC>
+__device__ __forceinline__ void mixed_tile_body(const SRC &S, int n, int n_act, double eps2,
+                                                int slice_len, const OutPtrs &out,
+                                                int64_t slice_stride, int ib, int sl) {
     __shared__ RecMixed tile[BLOCK];
     const int tid = threadIdx.x;
     const float eps2f = (float)eps2;
@@ -76,14 +75,12 @@ __device__ __forceinline__ void mixed_tile_body(const SrcPtrs &src,
         const int k = (ib * IPL + u) * BLOCK + tid;
         kid[u] = k;
         const int kc = k < n_act ? k : n_act - 1;
-        const int p = active ? active[kc] : kc;
+        const int p = S.target(kc);
         pid[u] = p;
+        double ad[3], jd[3];
+        S.template get<2>(p, xi[u], vi[u], ad, jd);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            xi[u][c] = src.x[c][p];
-            vi[u][c] = src.v[c][p];
-            ai[u][c] = (float)src.a[c][p];
-        }
+        for (int c = 0; c < 3; ++c) ai[u][c] = (float)ad[c];
     }
     double acc[IPL][9], hi[IPL][9], lo[IPL][9];
 #pragma unroll
@@ -99,11 +96,12 @@ __device__ __forceinline__ void mixed_tile_body(const SrcPtrs &src,
             const int jj = jt + tid;
             RecMixed r;
             if (jj < je) {
-                r.p0 = make_double2(src.x[0][jj], src.x[1][jj]);
-                r.p1 = make_double2(src.x[2][jj], src.v[0][jj]);
-                r.p2 = make_double2(src.v[1][jj], src.v[2][jj]);
-                r.am = make_float4((float)src.a[0][jj], (float)src.a[1][jj], (float)src.a[2][jj],
-                                   (float)src.m[jj]);
+                double xs[3], vs[3], as[3], jd[3];
+                S.template get<2>(jj, xs, vs, as, jd);
+                r.p0 = make_double2(xs[0], xs[1]);
+                r.p1 = make_double2(xs[2], vs[0]);
+                r.p2 = make_double2(vs[1], vs[2]);
+                r.am = make_float4((float)as[0], (float)as[1], (float)as[2], (float)S.mass(jj));
             } else {
                 r.p0 = make_double2(kPadPosMixed, kPadPosMixed);
                 r.p1 = make_double2(kPadPosMixed, 0.0);
@@ -166,12 +164,10 @@ __device__ __forceinline__ void mixed_tile_body(const SrcPtrs &src,
 // Small active sets: lanes over sources, TPW targets per wave (as the FP64
 // source-parallel kernel), FP32 pair arithmetic, FP32 partial sums over
 // kChunk sources per lane flushed into compensated FP64 pairs.
-template <int TPW, bool SKIPSELF>
-__device__ __forceinline__ void mixed_small_body(const SrcPtrs &src,
-                                                 const int32_t *__restrict__ active, int n,
-                                                 int n_act, double eps2, int slice_len,
-                                                 const OutPtrs &out, int64_t slice_stride,
-                                                 int wave, int sl) {
+template <int TPW, bool SKIPSELF, class SRC>
+__device__ __forceinline__ void mixed_small_body(const SRC &S, int n, int n_act, double eps2,
+                                                 int slice_len, const OutPtrs &out,
+                                                 int64_t slice_stride, int wave, int sl) {
     const int lane = threadIdx.x & 63;
     const float eps2f = (float)eps2;
     double xi[TPW][3], vi[TPW][3];
@@ -181,14 +177,12 @@ __device__ __forceinline__ void mixed_small_body(const SrcPtrs &src,
     for (int t = 0; t < TPW; ++t) {
         int k = wave * TPW + t;
         k = k < n_act ? k : n_act - 1;
-        const int p = active ? active[k] : k;
+        const int p = S.target(k);
         pid[t] = p;
+        double ad[3], jd[3];
+        S.template get<2>(p, xi[t], vi[t], ad, jd);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            xi[t][c] = src.x[c][p];
-            vi[t][c] = src.v[c][p];
-            ai[t][c] = (float)src.a[c][p];
-        }
+        for (int c = 0; c < 3; ++c) ai[t][c] = (float)ad[c];
     }
     float acc32[TPW][9];
     double hi[TPW][9], lo[TPW][9];
@@ -203,10 +197,12 @@ __device__ __forceinline__ void mixed_small_body(const SrcPtrs &src,
     const int je = min(n, jb + slice_len);
     int since_flush = 0;
     for (int j = jb + lane; j < je; j += 64) {
-        const double xj0 = src.x[0][j], xj1 = src.x[1][j], xj2 = src.x[2][j];
-        const double vj0 = src.v[0][j], vj1 = src.v[1][j], vj2 = src.v[2][j];
-        const float aj0 = (float)src.a[0][j], aj1 = (float)src.a[1][j], aj2 = (float)src.a[2][j];
-        const float mj = (float)src.m[j];
+        double xs[3], vs[3], as[3], jd[3];
+        S.template get<2>(j, xs, vs, as, jd);
+        const double xj0 = xs[0], xj1 = xs[1], xj2 = xs[2];
+        const double vj0 = vs[0], vj1 = vs[1], vj2 = vs[2];
+        const float aj0 = (float)as[0], aj1 = (float)as[1], aj2 = (float)as[2];
+        const float mj = (float)S.mass(j);
 #pragma unroll
         for (int t = 0; t < TPW; ++t) {
             const float dx = (float)(xj0 - xi[t][0]), dy = (float)(xj1 - xi[t][1]),
@@ -245,6 +241,27 @@ __device__ __forceinline__ void mixed_small_body(const SrcPtrs &src,
             if (lane == 0 && k < n_act) out.p[q][soff + k] = sv + cv;
         }
     }
+}
+
+// The bodies over predicted arrays (the host-shaped launches).
+template <int BLOCK, int IPL, bool SKIPSELF>
+__device__ __forceinline__ void mixed_tile_body(const SrcPtrs &src,
+                                                const int32_t *__restrict__ active, int n,
+                                                int n_act, double eps2, int slice_len,
+                                                const OutPtrs &out, int64_t slice_stride, int ib,
+                                                int sl) {
+    mixed_tile_body<BLOCK, IPL, SKIPSELF>(evalbody::PredSrc{src, active}, n, n_act, eps2,
+                                          slice_len, out, slice_stride, ib, sl);
+}
+
+template <int TPW, bool SKIPSELF>
+__device__ __forceinline__ void mixed_small_body(const SrcPtrs &src,
+                                                 const int32_t *__restrict__ active, int n,
+                                                 int n_act, double eps2, int slice_len,
+                                                 const OutPtrs &out, int64_t slice_stride,
+                                                 int wave, int sl) {
+    mixed_small_body<TPW, SKIPSELF>(evalbody::PredSrc{src, active}, n, n_act, eps2, slice_len,
+                                    out, slice_stride, wave, sl);
 }
 
 }  // namespace mixedbody

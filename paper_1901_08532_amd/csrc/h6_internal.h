@@ -18,6 +18,7 @@ constexpr int kTickBits = H6_TICK_BITS;
 // Device status flags (bit set in ctx->flags[0]).
 constexpr int kFlagDtMin = 1;
 constexpr int kFlagNonFinite = 2;
+constexpr int kFlagLoop = 4;  // block-loop bookkeeping out of range (internal error)
 
 // Source (j-side) arrays of an evaluation, structure of arrays.
 struct SrcPtrs {
@@ -32,18 +33,58 @@ struct OutPtrs {
     double *p[kMaxOut];
 };
 
-// Per-block descriptor of the device-resident block loop, written by the
-// scheduler's last workgroup and read by the later kernels of the block.
-struct BlockDesc {
-    int64_t t_next;     // block time (ticks)
-    int32_t n_act;      // active particles; 0 = nothing to do
-    int32_t done;       // 1 once t_next would pass t_end
-    int32_t kind;       // evaluation kind: 0 tile, 1 source-parallel
-    int32_t groups;     // target groups (tile: 128 targets; source-parallel: 1)
-    int32_t split;      // source slices
-    int32_t slice_len;  // sources per slice
-    int64_t blocks;     // non-empty blocks since the loop started
-    int64_t particle_steps;  // sum of n_act since the loop started
+// ---- device-resident block loop (blockloop.hip)
+constexpr int kLevels = kTickBits + 1;  // levels 0..40: step 2^-level
+constexpr int kSmall2Max = 128;         // largest active set of the source-parallel kinds
+
+// Plan of one block, written by the plan of the block before (double
+// buffered by block parity) and read by the kernels of the block.
+struct LoopDesc {
+    int64_t t_next;          // block time (ticks)
+    int64_t blocks;          // non-empty blocks planned since the loop started
+    int64_t particle_steps;  // sum of their active counts
+    uint64_t sel;            // bit L: list buffer holding level L
+    int32_t n_act;           // active particles; 0 = nothing to do
+    int32_t done;            // 1 once t_next would pass t_end
+    int32_t invalid;         // set-up found a state off the block grid
+    int32_t kind;            // evaluation kind: 0 tile, 1 one target per wave, 3 two
+    int32_t groups;          // target groups
+    int32_t split;           // source slices
+    int32_t slice_len;       // sources per slice
+    int32_t L0;              // lowest active level
+    int32_t lv_hi;           // highest occupied level
+    int32_t cnt[kLevels];    // particles per level
+    int32_t off[kLevels];    // first active rank of level L (L >= L0)
+};
+
+// Counters of the loop (device, zero between blocks).
+struct LoopScratch {
+    unsigned done_fin;             // finishing workgroups done
+    unsigned app;                  // particles appended to level L0 - 1
+    unsigned bad;                  // set-up: particles off the block grid
+    unsigned reb[kLevels];         // sizes of the rebuilt lists (set-up: fill)
+    unsigned long long t_max;      // set-up: latest particle time
+    unsigned long long due_min;    // set-up: earliest t + dt
+};
+
+// Arguments of every loop kernel.
+struct LoopArgs {
+    h6_state st;
+    int n;
+    int lev_lo, nl;       // list levels lev_lo .. lev_lo + nl - 1
+    int32_t *lists;       // [2][nl][n]
+    LoopDesc *desc;       // [2]
+    LoopScratch *scr;
+    double *partial;      // [split][9][n_act]
+    h6_pred pred;         // predicted x, v, a (tile kind)
+    double eps2, eta6;
+    int lev_min, lev_max;
+    int64_t t_end;
+    int eval_grid;
+    int64_t partial_cap;
+    int32_t *flags;
+    int32_t *nact_log;    // n_act by block sequence number (ring), or NULL
+    int log_mask;
 };
 
 struct EvalConfig {
@@ -76,7 +117,10 @@ struct h6_ctx_s {
     void *host = nullptr;
     std::string last_error;
     // device-resident block loop
-    h6::BlockDesc *bl_desc = nullptr;  // device
+    h6::LoopDesc *bl_desc = nullptr;     // device, [2]
+    h6::LoopScratch *bl_scr = nullptr;   // device
+    int32_t *bl_lists = nullptr;         // device level lists
+    int64_t bl_lists_cap = 0;            // ints
     int32_t *bl_log = nullptr;     // n_act per block sequence number (ring), profiling only
     int bl_log_mask = 0;
     hipEvent_t bl_ev[2] = {nullptr, nullptr};
@@ -132,20 +176,22 @@ hipError_t launch_correct_shared_vjp(h6_ctx ctx, h6_state *cot, int n, const h6_
 hipError_t launch_predict_dt_vjp(h6_ctx ctx, h6_state *cot, int n, const h6_pred *cp, double dt);
 
 int sched_blocks_for(int64_t n);
-// Measurement hook helpers (api.hip).
+// Measurement hook helpers (api.hip). prof_begin / prof_end bracket a
+// launch with recorded events; prof_events hands out an event pair for a
+// launch that records them itself (hipExtLaunchKernel), prof_push_seq
+// queues such a pair for a device-loop block.
+hipError_t prof_events(h6_ctx ctx, hipEvent_t *e0, hipEvent_t *e1);
 hipError_t prof_begin(h6_ctx ctx, hipEvent_t *e0, hipEvent_t *e1);
 hipError_t prof_end(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int order, const EvalConfig &cfg,
                     int precision, int64_t n_act, double interactions);
-hipError_t prof_end_seq(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int precision, int64_t seq);
+hipError_t prof_push_seq(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int precision, int64_t seq);
 hipError_t prof_resolve(h6_ctx ctx);  // stream must be idle
 
 // Device-resident block loop (blockloop.hip).
-int bl_select_blocks(int64_t n);
 int bl_eval_grid(h6_ctx ctx);
-hipError_t bl_reset(h6_ctx ctx);
-hipError_t bl_enqueue_block(h6_ctx ctx, h6_state *st, int n, const h6_pred *pred,
-                            const h6_force *f, int32_t *active, const h6_params *prm,
-                            int64_t t_end, int64_t seq);
+int64_t bl_list_ints(int64_t n, int nl);  // list storage for n particles on nl levels
+hipError_t bl_setup(h6_ctx ctx, const LoopArgs &A);  // lists and the plan of block 0
+hipError_t bl_enqueue_block(h6_ctx ctx, const LoopArgs &A, int precision, int64_t seq);
 int energy_blocks_for(int64_t n);
 
 }  // namespace h6

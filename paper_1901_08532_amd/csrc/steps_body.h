@@ -40,43 +40,53 @@ __device__ __forceinline__ double norm3(double a, double b, double c) {
 // ---------------------------------------------------------------- predictor
 // Taylor prediction of particle i over interval d: x to 5th order, v to
 // 4th, a to 3rd, Horner form.
-__device__ __forceinline__ void predict_one(const h6_state &st, int i, double d,
-                                            const h6_pred &out) {
+__device__ __forceinline__ void predict_vals(const h6_state &st, int i, double d, double *xo,
+                                             double *vo, double *ao) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const double x = st.x[c][i], v = st.v[c][i], a = st.a[c][i];
         const double j = st.j[c][i], s = st.s[c][i], cr = st.c[c][i];
         // a_p = a + d (j + d/2 (s + d/3 c))
-        const double ap = fma(d, fma(d * 0.5, fma(d * (1.0 / 3.0), cr, s), j), a);
+        ao[c] = fma(d, fma(d * 0.5, fma(d * (1.0 / 3.0), cr, s), j), a);
         // v_p = v + d (a + d/2 (j + d/3 (s + d/4 c)))
-        const double vp =
-            fma(d, fma(d * 0.5, fma(d * (1.0 / 3.0), fma(d * 0.25, cr, s), j), a), v);
+        vo[c] = fma(d, fma(d * 0.5, fma(d * (1.0 / 3.0), fma(d * 0.25, cr, s), j), a), v);
         // x_p = x + d (v + d/2 (a + d/3 (j + d/4 (s + d/5 c))))
-        const double xp = fma(
+        xo[c] = fma(
             d, fma(d * 0.5, fma(d * (1.0 / 3.0), fma(d * 0.25, fma(d * 0.2, cr, s), j), a), v), x);
-        out.x[c][i] = xp;
-        out.v[c][i] = vp;
-        out.a[c][i] = ap;
+    }
+}
+
+__device__ __forceinline__ void predict_one(const h6_state &st, int i, double d,
+                                            const h6_pred &out) {
+    double xp[3], vp[3], ap[3];
+    predict_vals(st, i, d, xp, vp, ap);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        out.x[c][i] = xp[c];
+        out.v[c][i] = vp[c];
+        out.a[c][i] = ap[c];
     }
 }
 
 // ---------------------------------------------------------------- corrector
 // 6th-order Hermite corrector, quintic interpolation of crackle, pop and
 // the fifth derivative at the step end, and the power-of-two step rule.
-// Corrects particle i (k: its index in the force arrays) with the new
-// a1, j1, s1 (fa, fj, fs); shared steps use the fixed step dt_sh and keep
-// t and dt, block steps take the step from dt[i] and assign the new one.
+// Computes, for particle i and the new a1, j1, s1 (fa, fj, fs), the
+// corrected x1, v1 and the interpolated crackle c1; block steps (SHARED
+// false) also the new level (step 2^-level), taking the step from dt[i].
+// Reads the state only.
 template <bool SHARED>
-__device__ __forceinline__ void correct_one(const h6_state &st, int i, const double *fa,
-                                            const double *fj, const double *fs, int64_t t_next,
-                                            double dt_sh, double eta6, int lev_min, int lev_max,
-                                            int32_t *flags) {
+__device__ __forceinline__ void correct_vals(const h6_state &st, int i, const double *fa,
+                                             const double *fj, const double *fs, int64_t t_next,
+                                             double dt_sh, double eta6, int lev_min, int lev_max,
+                                             int32_t *flags, double *x1o, double *v1o,
+                                             double *c1o, int *lev_out) {
     const int64_t dt_old = SHARED ? 0 : st.dt[i];
     const double h = SHARED ? dt_sh : (double)dt_old * kTick;
     const double h2 = h * h;
     const double hinv = 1.0 / h;
     const double hinv2 = hinv * hinv, hinv3 = hinv2 * hinv;
-    double a1n[3], j1n[3], s1n[3], cn[3], pn[3], dn[3];
+    double pn[3], dn[3];
     bool finite = true;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -92,33 +102,22 @@ __device__ __forceinline__ void correct_one(const h6_state &st, int i, const dou
         const double da = a1 - a0;
         // derivatives of the quintic through (a, j, s) at both ends, at the end
         const double c1 = fma(h2, 9.0 * s1 - 3.0 * s0, fma(-h, fma(24.0, j0, 36.0 * j1), 60.0 * da)) * hinv3;
-        st.x[c][i] = x1;
-        st.v[c][i] = v1;
-        st.a[c][i] = a1;
-        st.j[c][i] = j1;
-        st.s[c][i] = s1;
-        st.c[c][i] = c1;
+        x1o[c] = x1;
+        v1o[c] = v1;
+        c1o[c] = c1;
         finite = finite && isfinite(x1) && isfinite(v1) && isfinite(c1);
         if (!SHARED) {
-            const double p1 =
-                fma(h2, 36.0 * s1 - 24.0 * s0, fma(-h, fma(168.0, j0, 192.0 * j1), 360.0 * da)) *
-                (hinv3 * hinv);
-            const double d5 =
-                fma(60.0 * h2, s1 - s0, fma(-360.0 * h, j0 + j1, 720.0 * da)) * (hinv3 * hinv2);
-            a1n[c] = a1;
-            j1n[c] = j1;
-            s1n[c] = s1;
-            cn[c] = c1;
-            pn[c] = p1;
-            dn[c] = d5;
+            pn[c] = fma(h2, 36.0 * s1 - 24.0 * s0, fma(-h, fma(168.0, j0, 192.0 * j1), 360.0 * da)) *
+                    (hinv3 * hinv);
+            dn[c] = fma(60.0 * h2, s1 - s0, fma(-360.0 * h, j0 + j1, 720.0 * da)) * (hinv3 * hinv2);
         }
     }
     if (!finite) atomicOr(flags, kFlagNonFinite);
     if (SHARED) return;
     // generalized Aarseth criterion, order 6: dt^6 = eta^6 A1 / A4
-    const double A1 = fma(norm3(a1n[0], a1n[1], a1n[2]), norm3(s1n[0], s1n[1], s1n[2]),
-                          fma(j1n[0], j1n[0], fma(j1n[1], j1n[1], j1n[2] * j1n[2])));
-    const double A4 = fma(norm3(cn[0], cn[1], cn[2]), norm3(dn[0], dn[1], dn[2]),
+    const double A1 = fma(norm3(fa[0], fa[1], fa[2]), norm3(fs[0], fs[1], fs[2]),
+                          fma(fj[0], fj[0], fma(fj[1], fj[1], fj[2] * fj[2])));
+    const double A4 = fma(norm3(c1o[0], c1o[1], c1o[2]), norm3(dn[0], dn[1], dn[2]),
                           fma(pn[0], pn[0], fma(pn[1], pn[1], pn[2] * pn[2])));
     const double q = (A1 / A4) * eta6;
     const int lev_crit = level_from_power(q, 6, lev_min, lev_max + 1);
@@ -134,8 +133,32 @@ __device__ __forceinline__ void correct_one(const h6_state &st, int i, const dou
         atomicOr(flags, kFlagDtMin);
         lev_new = lev_max;
     }
+    *lev_out = lev_new;
+}
+
+// correct_vals, stored in place: x, v, c corrected, a, j, s the new
+// values; block steps also set t = t_next and the new step.
+template <bool SHARED>
+__device__ __forceinline__ void correct_one(const h6_state &st, int i, const double *fa,
+                                            const double *fj, const double *fs, int64_t t_next,
+                                            double dt_sh, double eta6, int lev_min, int lev_max,
+                                            int32_t *flags) {
+    double x1[3], v1[3], c1[3];
+    int lev = 0;
+    correct_vals<SHARED>(st, i, fa, fj, fs, t_next, dt_sh, eta6, lev_min, lev_max, flags, x1, v1,
+                         c1, &lev);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        st.x[c][i] = x1[c];
+        st.v[c][i] = v1[c];
+        st.a[c][i] = fa[c];
+        st.j[c][i] = fj[c];
+        st.s[c][i] = fs[c];
+        st.c[c][i] = c1[c];
+    }
+    if (SHARED) return;
     st.t[i] = t_next;
-    st.dt[i] = (int64_t)1 << (kTickBits - lev_new);
+    st.dt[i] = (int64_t)1 << (kTickBits - lev);
 }
 
 }  // namespace stepbody

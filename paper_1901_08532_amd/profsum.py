@@ -27,8 +27,8 @@ from collections import defaultdict
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1901_08532_amd", "csrc")
 # the evaluation kernels' sources (the same list as bench.py checks)
-EVAL_SOURCES = ("eval_body.h", "eval_mixed_body.h", "device_math.h", "blockloop.hip", "eval.hip",
-                "eval_mixed.hip")
+EVAL_SOURCES = ("eval_body.h", "eval_mixed_body.h", "device_math.h", "steps_body.h",
+                "blockloop.hip", "eval.hip", "eval_mixed.hip")
 
 
 def eval_sources_sha256():

@@ -31,10 +31,10 @@ def _from_oracle(st):
     return sysg
 
 
-@pytest.mark.parametrize("n", [33, 1000, 5000])
-def test_device_loop_matches_oracle_blocks(n):
+@pytest.mark.parametrize("n,eps", [(33, EPS), (1000, EPS), (5000, EPS), (200, 0.0)])
+def test_device_loop_matches_oracle_blocks(n, eps):
     x, v, m = ics.plummer(n, 100 + n)
-    st = oracle.State(x, v, m, EPS ** 2)
+    st = oracle.State(x, v, m, eps ** 2)
     assert st.startup(eta_s=0.1, lev_min=4, lev_max=30) == 0
     sysg = _from_oracle(st)
     nblk = psteps = 0
@@ -115,3 +115,55 @@ def test_device_loop_profile_records():
     assert sum(r["launches"] for r in real) == st.blocks
     assert sum(r["interactions"] for r in real) == pytest.approx(st.interactions)
     assert all(r["kernel_ms"] > 0 for r in real)
+
+
+def _host_vs_device(s_dev, s_host, t_end, lev_min, lev_max):
+    rd, sd = s_dev.run_blocks(t_end, 0.4, lev_min, lev_max)
+    rh, sh = s_host.run_blocks(t_end, 0.4, lev_min, lev_max, host_loop=True)
+    assert rd == rh == h6.H6_OK
+    assert (sd.blocks, sd.particle_steps) == (sh.blocks, sh.particle_steps)
+    assert torch.equal(s_dev.T, s_host.T) and torch.equal(s_dev.S, s_host.S)
+
+
+def _pair(n, seed):
+    x, v, m = ics.plummer(n, seed)
+    a = h6.System(x, v, m, EPS)
+    a.startup(eta_s=0.1, lev_min=4, lev_max=30)
+    b = h6.System(x, v, m, EPS)
+    b.S.copy_(a.S)
+    b.T.copy_(a.T)
+    return a, b
+
+
+def test_device_loop_off_grid_state_uses_host_loop():
+    # a particle time that is not a multiple of its step: the level lists do
+    # not apply, and the call runs the host-sequenced loop (bitwise the same)
+    a, b = _pair(2000, 21)
+    for s in (a, b):
+        s.T[0, 7] = s.T[1, 7] // 2
+    _host_vs_device(a, b, SYNC, 4, 30)
+
+
+def test_device_loop_levels_outside_run_range_use_host_loop():
+    # start-up steps taken with lev_max 30; a run limited to two levels below
+    # the deepest one cannot list those particles and falls back to the host
+    # loop (which clamps their steps and reports H6_EDTMIN)
+    a, b = _pair(2000, 22)
+    lev = h6.TICK_BITS - torch.log2(a.T[1].double()).round().long()
+    top = int(lev.max()) - 2
+    assert top > 4
+    ra, _ = a.run_blocks(SYNC, 0.4, 4, top, check=False)
+    rb, _ = b.run_blocks(SYNC, 0.4, 4, top, check=False, host_loop=True)
+    assert ra == rb
+    assert torch.equal(a.T, b.T) and torch.equal(a.S, b.S)
+
+
+def test_device_loop_single_particle_and_tiny_systems():
+    for n in (1, 2, 3):
+        x, v, m = ics.plummer(max(n, 2), 30 + n)
+        x, v, m = x[:n], v[:n], m[:n]
+        s = h6.System(x, v, m, EPS)
+        s.startup(eta_s=0.1, lev_min=4, lev_max=30)
+        rc, st = s.run_blocks(SYNC, 0.4, 4, 30)
+        assert rc == h6.H6_OK and st.blocks > 0
+        assert bool((s.T[0] == SYNC).all())
