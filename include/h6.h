@@ -117,14 +117,15 @@ int h6_destroy(h6_ctx ctx);
 int h6_set_stream(h6_ctx ctx, void *hip_stream);
 
 /*
- * Launch shape of the evaluation. Active sets of at most small_max targets
- * go to a source-parallel kernel (lanes over sources, no LDS); larger ones
- * to the LDS-tiled target-parallel kernel with the given threads per
- * workgroup (64, 128 or 256), targets per thread (1 or 2) and number of
- * source slices the sum is split into (>= 1). 0 keeps the built-in choice
- * for block, ipl and n_split; small_max < 0 keeps the built-in threshold and
- * 0 disables the small-set kernel. Results agree to rounding for every
- * shape. Errors: H6_EINVAL.
+ * Launch shape of h6_evaluate. Active sets of at most small_max targets go
+ * to a source-parallel kernel (lanes over sources, no LDS) with ipl targets
+ * per wave (1, 2 or 4); larger ones to the LDS-tiled target-parallel kernel
+ * with the given threads per workgroup (64, 128 or 256) and targets per
+ * thread (1 or 2; 4 counts as 2 there). n_split: number of source slices
+ * the sum is split into (>= 1). 0 keeps the built-in choice for block, ipl
+ * and n_split; small_max < 0 keeps the built-in threshold and 0 disables
+ * the small-set kernel. Results agree to rounding for every shape. The
+ * device-resident block loop chooses its own shapes. Errors: H6_EINVAL.
  */
 int h6_set_eval_config(h6_ctx ctx, int block, int ipl, int n_split,
                        int small_max);

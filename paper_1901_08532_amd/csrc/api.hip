@@ -305,7 +305,8 @@ int h6_set_eval_config(h6_ctx ctx, int block, int ipl, int n_split, int small_ma
     if (!ctx) return H6_EINVAL;
     if (block != 0 && block != 64 && block != 128 && block != 256)
         return fail_arg(ctx, "block must be 0, 64, 128 or 256");
-    if (ipl != 0 && ipl != 1 && ipl != 2) return fail_arg(ctx, "ipl must be 0, 1 or 2");
+    if (ipl != 0 && ipl != 1 && ipl != 2 && ipl != 4)
+        return fail_arg(ctx, "ipl must be 0, 1, 2 or 4");
     if (n_split < 0) return fail_arg(ctx, "n_split must be >= 0");
     ctx->cfg_block = block;
     ctx->cfg_ipl = ipl;
@@ -516,7 +517,7 @@ static int run_blocks_device(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred 
     A.lev_max = prm->lev_max;
     A.t_end = t_end;
     A.eval_grid = bl_eval_grid(ctx);
-    A.partial_cap = ctx->partial_cap;
+    A.pc_pairs = (unsigned)(ctx->partial_cap / 9);
     A.flags = ctx->flags;
     A.nact_log = ctx->prof ? ctx->bl_log : nullptr;
     A.log_mask = ctx->bl_log_mask;

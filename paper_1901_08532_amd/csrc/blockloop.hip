@@ -49,12 +49,10 @@ using namespace stepbody;
 constexpr int kSmall1Max = 16;   // active sets up to this size: one target per wave
 constexpr int kTileBlock = 64;   // tile kind: one wave, two targets per lane
 constexpr int kTileIpl = 2;
-constexpr int kWaveReduce = 24;  // slices from which waves reduce (target, component) jobs
 constexpr int kFinThreads = 512;
 constexpr int kFinGrid = 128;    // finishing workgroups at most
 constexpr int kScanThreads = 256;
 
-__device__ __forceinline__ int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 template <typename T>
 __device__ __forceinline__ T load_agent(const T *p) {
@@ -162,44 +160,55 @@ struct ListPredSrc {
     __device__ __forceinline__ double mass(int p) const { return A.st.m[p]; }
 };
 
-// Evaluation shape for n_act targets. Source-parallel kinds (1: one target
-// per wave, 3: two): slices of at least 256 sources (4 per lane), at most
-// eval_grid waves in all. Tile kind 0 (128 targets per one-wave workgroup):
-// the largest slice count whose units fit one round of resident workgroups,
-// at least four 64-source tiles per slice. Bounded by the partial capacity.
-__device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, int64_t partial_cap) {
+__device__ __forceinline__ int cdiv32(int a, int b) { return (a + b - 1) / b; }
+
+// Evaluation shape for n_act targets (32-bit arithmetic: one thread runs
+// it on the critical path). Source-parallel kinds (1: one target per wave,
+// 3: two), which predict on the fly: slices of at least 256 sources (4 per
+// lane), at most eval_grid waves in all. Tile kind 0 (128 targets per
+// one-wave workgroup, predicted arrays): as many slices as fit one round of
+// resident workgroups, down to one 64-source tile per slice (measured on
+// gfx950: for a few hundred targets, one-tile slices over the whole grid
+// beat fewer, longer ones by a third). pc_pairs bounds split * n_act.
+__device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsigned pc_pairs) {
     int split, kind, groups;
     if (n_act <= kSmall2Max) {
         kind = n_act <= kSmall1Max ? 1 : 3;
-        groups = kind == 1 ? n_act : cdiv(n_act, 2);
-        split = cdiv(n, 256);
+        groups = kind == 1 ? n_act : cdiv32(n_act, 2);
+        split = (n + 255) >> 8;
         const int fit = eval_grid / groups;
         split = split < fit ? split : fit;
     } else {
         kind = 0;
-        groups = cdiv(n_act, kTileBlock * kTileIpl);
+        groups = cdiv32(n_act, kTileBlock * kTileIpl);
         split = eval_grid / groups;
-        const int cap = n / (4 * kTileBlock);
+        const int cap = (n + kTileBlock - 1) / kTileBlock;
         split = split < cap ? split : cap;
     }
-    const int64_t pc = partial_cap / ((int64_t)9 * n_act);
-    if (split > pc) split = (int)pc;
+    const unsigned pc = pc_pairs / (unsigned)n_act;
+    if ((unsigned)split > pc) split = (int)pc;
     if (split < 1) split = 1;
-    const int slice = cdiv(cdiv(n, split), 64) * 64;
+    const int slice = cdiv32(cdiv32(n, split), 64) * 64;
     d->kind = kind;
     d->groups = groups;
     d->slice_len = slice;
-    d->split = cdiv(n, slice);
+    d->split = cdiv32(n, slice);
 }
 
-// Targets per finishing workgroup round (many slices: one wave per target;
-// few: one thread per target) and the number of finishing workgroups with
-// work, for a block of n_act targets in `split` slices.
+// Lanes per target in the finishing reduction: the power of two covering
+// the slices, at most a wave; a wave sums 64 / seg targets at once.
+__device__ __forceinline__ int fin_seg(int split) {
+    int seg = 1;
+    while (seg < split && seg < 64) seg <<= 1;
+    return seg;
+}
+// Targets per finishing workgroup round and the number of finishing
+// workgroups with work, for a block of n_act targets in `split` slices.
 __device__ __forceinline__ int fin_per_round(int split) {
-    return split >= kWaveReduce ? kFinThreads / 64 : kFinThreads;
+    return (64 / fin_seg(split)) * (kFinThreads / 64);
 }
 __device__ __forceinline__ int fin_workers(int n_act, int split) {
-    const int w = cdiv(n_act, fin_per_round(split));
+    const int w = cdiv32(n_act, fin_per_round(split));
     return w < kFinGrid ? w : kFinGrid;
 }
 
@@ -214,8 +223,9 @@ __device__ void plan_block(const LoopArgs &A, LoopDesc *d, const int *cnt, int64
     int lv_hi = -1;
     for (int L = A.lev_lo; L < A.lev_lo + A.nl; ++L) {
         if (cnt[L] > 0) {
-            const int64_t dtl = (int64_t)1 << (kTickBits - L);
-            const int64_t cand = (t_cur / dtl + 1) * dtl;
+            // next multiple of 2^(40 - L) ticks after t_cur (t_cur >= 0)
+            const int sh = kTickBits - L;
+            const int64_t cand = ((t_cur >> sh) + 1) << sh;
             tn = cand < tn ? cand : tn;
             lv_hi = L;
         }
@@ -237,7 +247,7 @@ __device__ void plan_block(const LoopArgs &A, LoopDesc *d, const int *cnt, int64
         }
         d->L0 = L0;
         d->done = 0;
-        launch_shape(d, A.n, n_act, A.eval_grid, A.partial_cap);
+        launch_shape(d, A.n, n_act, A.eval_grid, A.pc_pairs);
         blocks += 1;
         psteps += n_act;
     }
@@ -312,10 +322,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     if (n_act == 0) return;
     const int split = d->split, slice_len = d->slice_len, groups = d->groups;
     const int kind = d->kind;
+    // slice sums at partial[(k * 9 + c) * split + sl]: a target's slices are
+    // contiguous for the finishing reduction
     OutPtrs out;
 #pragma unroll
-    for (int c = 0; c < kMaxOut; ++c) out.p[c] = c < 9 ? A.partial + (int64_t)c * n_act : nullptr;
-    const int64_t slice_stride = (int64_t)9 * n_act;
+    for (int c = 0; c < kMaxOut; ++c) out.p[c] = c < 9 ? A.partial + (int64_t)c * split : nullptr;
+    out.kstride = (int64_t)9 * split;
+    const int64_t slice_stride = 1;
     const int units = groups * split;
     if ((int)blockIdx.x >= units) return;
     __shared__ RankTable rt;
@@ -419,6 +432,7 @@ __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t s
         return;
     }
     const int split = d->split;
+    const int seg = fin_seg(split);
     const int per = fin_per_round(split);
     const int workers = fin_workers(n_act, split);
     if ((int)blockIdx.x >= workers) return;
@@ -440,61 +454,37 @@ __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t s
         const bool valid = tid < nt;
         int id = 0, lev = 0;
         if (valid) id = rank_to_particle(A, &rt, k0 + tid);  // overlaps the slice loads
-        const double *__restrict__ part = A.partial;
-        if (split >= kWaveReduce) {
-            // one wave per target: lanes over slices, the nine components'
-            // loads of four slices per lane issued together, then a fixed
-            // butterfly each
-            if (w < nt) {
-                const int64_t k = k0 + w;
-                double s[9], comp[9];
-#pragma unroll
-                for (int c = 0; c < 9; ++c) s[c] = comp[c] = 0.0;
-                for (int sl0 = 0; sl0 < split; sl0 += 256) {
-                    double x[4][9];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int sl = sl0 + q * 64 + lane;
-#pragma unroll
-                        for (int c = 0; c < 9; ++c)
-                            x[q][c] = sl < split ? part[((int64_t)sl * 9 + c) * n_act + k] : 0.0;
-                    }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-#pragma unroll
-                        for (int c = 0; c < 9; ++c) neumaier(s[c], comp[c], x[q][c]);
-                }
-#pragma unroll
-                for (int c = 0; c < 9; ++c) {
-                    wave_comp_sum(s[c], comp[c]);
-                    if (lane == 0) fs[w * 9 + c] = s[c] + comp[c];
-                }
-            }
-        } else if (valid) {
-            // one thread per target, slices in order, four slices' loads at once
-            const int64_t k = k0 + tid;
+        {
+            // seg lanes per target (contiguous slices: coalesced loads), the
+            // nine components' loads of four passes issued together, then a
+            // fixed butterfly within the segment
+            const double *__restrict__ part = A.partial;
+            const int r = w * (64 / seg) + lane / seg;  // target of this lane in the round
+            const int o = lane & (seg - 1);
+            const bool has = r < nt;
+            const int64_t base = (int64_t)(k0 + (has ? r : 0)) * 9 * split;
             double s[9], comp[9];
 #pragma unroll
             for (int c = 0; c < 9; ++c) s[c] = comp[c] = 0.0;
-            int sl = 0;
-            for (; sl + 4 <= split; sl += 4) {
+            for (int sl0 = 0; sl0 < split; sl0 += 4 * seg) {
                 double x[4][9];
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                for (int q = 0; q < 4; ++q) {
+                    const int sl = sl0 + q * seg + o;
+                    const bool in = has && sl < split;
 #pragma unroll
-                    for (int c = 0; c < 9; ++c)
-                        x[q][c] = part[((int64_t)(sl + q) * 9 + c) * n_act + k];
+                    for (int c = 0; c < 9; ++c) x[q][c] = in ? part[base + c * split + sl] : 0.0;
+                }
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll
                     for (int c = 0; c < 9; ++c) neumaier(s[c], comp[c], x[q][c]);
             }
-            for (; sl < split; ++sl)
 #pragma unroll
-                for (int c = 0; c < 9; ++c)
-                    neumaier(s[c], comp[c], part[((int64_t)sl * 9 + c) * n_act + k]);
-#pragma unroll
-            for (int c = 0; c < 9; ++c) fs[tid * 9 + c] = s[c] + comp[c];
+            for (int c = 0; c < 9; ++c) {
+                seg_comp_sum(s[c], comp[c], seg);
+                if (has && o == 0) fs[r * 9 + c] = s[c] + comp[c];
+            }
         }
         __syncthreads();
         if (valid) {

@@ -54,4 +54,20 @@ __device__ __forceinline__ void wave_comp_sum(double &s, double &c) {
     }
 }
 
+// The same butterfly within aligned segments of seg lanes (seg a power of
+// two up to 64, uniform across the wave): every lane gets its segment's
+// total.
+__device__ __forceinline__ void seg_comp_sum(double &s, double &c, int seg) {
+    const int lane = threadIdx.x & 63;
+    for (int off = seg >> 1; off >= 1; off >>= 1) {
+        const double s2 = __shfl_xor(s, off, 64);
+        const double c2 = __shfl_xor(c, off, 64);
+        double a = (lane & off) ? s2 : s, ac = (lane & off) ? c2 : c;
+        const double b = (lane & off) ? s : s2, bc = (lane & off) ? c : c2;
+        comp_merge(a, ac, b, bc);
+        s = a;
+        c = ac;
+    }
+}
+
 }  // namespace h6

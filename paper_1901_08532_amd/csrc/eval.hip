@@ -212,11 +212,12 @@ EvalConfig choose_eval_config(h6_ctx ctx, int order, int precision, int n, int n
         // source-parallel kernel: one wave per TPW targets
         cfg.kind = 1;
         cfg.block = 64;
-        cfg.ipl = n_act <= 4 ? 1 : 2;
+        cfg.ipl = ctx->cfg_ipl ? ctx->cfg_ipl : (n_act <= 4 ? 1 : 2);
         const int waves_i = ceil_div(n_act, cfg.ipl);
         int split = ceil_div(kTargetWaves, waves_i);
         const int max_split = ceil_div(n, kSmallMinSlice);
         if (split > max_split) split = max_split;
+        if (ctx->cfg_split) split = ctx->cfg_split < ceil_div(n, 64) ? ctx->cfg_split : ceil_div(n, 64);
         const int64_t cap_split = ctx->partial_cap / ((int64_t)9 * n_act);
         if (split > cap_split) split = (int)cap_split;
         cfg.n_split = split < 1 ? 1 : split;
@@ -230,7 +231,7 @@ EvalConfig choose_eval_config(h6_ctx ctx, int order, int precision, int n, int n
         // measured on gfx950 at N = 65536: one target per lane in 64-thread
         // workgroups up to 512 targets, two per lane beyond
         cfg.block = ctx->cfg_block ? ctx->cfg_block : (n_act <= 16384 ? 64 : 256);
-        cfg.ipl = ctx->cfg_ipl ? ctx->cfg_ipl : (n_act <= 512 ? 1 : 2);
+        cfg.ipl = ctx->cfg_ipl ? (ctx->cfg_ipl > 2 ? 2 : ctx->cfg_ipl) : (n_act <= 512 ? 1 : 2);
     }
     const int per_block = cfg.block * cfg.ipl;
     const int blocks_i = ceil_div(n_act, per_block);

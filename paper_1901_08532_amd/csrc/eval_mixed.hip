@@ -71,6 +71,7 @@ hipError_t dispatch_mixed(const EvalConfig &cfg, bool skipself, dim3 grid, hipSt
     }
         H6_SMALLM(1)
         H6_SMALLM(2)
+        H6_SMALLM(4)
 #undef H6_SMALLM
         return hipErrorInvalidValue;
     }

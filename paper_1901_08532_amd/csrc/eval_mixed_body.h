@@ -158,7 +158,7 @@ __device__ __forceinline__ void mixed_tile_body(const SRC &S, int n, int n_act, 
     for (int u = 0; u < IPL; ++u)
         if (kid[u] < n_act)
 #pragma unroll
-            for (int q = 0; q < 9; ++q) out.p[q][soff + kid[u]] = hi[u][q] + lo[u][q];
+            for (int q = 0; q < 9; ++q) out.p[q][soff + kid[u] * out.kstride] = hi[u][q] + lo[u][q];
 }
 
 // Small active sets: lanes over sources, TPW targets per wave (as the FP64
@@ -238,7 +238,7 @@ __device__ __forceinline__ void mixed_small_body(const SRC &S, int n, int n_act,
             double sv = hi[t][q], cv = lo[t][q];
             wave_comp_sum(sv, cv);
             const int k = wave * TPW + t;
-            if (lane == 0 && k < n_act) out.p[q][soff + k] = sv + cv;
+            if (lane == 0 && k < n_act) out.p[q][soff + k * out.kstride] = sv + cv;
         }
     }
 }

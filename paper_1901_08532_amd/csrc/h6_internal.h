@@ -27,15 +27,16 @@ struct SrcPtrs {
 };
 
 // Output arrays by component: component c of target k of slice s lives at
-// p[c][s * slice_stride + k].
+// p[c][s * slice_stride + k * kstride].
 constexpr int kMaxOut = 16;
 struct OutPtrs {
     double *p[kMaxOut];
+    int64_t kstride = 1;
 };
 
 // ---- device-resident block loop (blockloop.hip)
 constexpr int kLevels = kTickBits + 1;  // levels 0..40: step 2^-level
-constexpr int kSmall2Max = 128;         // largest active set of the source-parallel kinds
+constexpr int kSmall2Max = 48;          // largest active set of the source-parallel kinds
 
 // Plan of one block, written by the plan of the block before (double
 // buffered by block parity) and read by the kernels of the block.
@@ -81,7 +82,7 @@ struct LoopArgs {
     int lev_min, lev_max;
     int64_t t_end;
     int eval_grid;
-    int64_t partial_cap;
+    unsigned pc_pairs;    // partial capacity / 9: bound on split * n_act
     int32_t *flags;
     int32_t *nact_log;    // n_act by block sequence number (ring), or NULL
     int log_mask;

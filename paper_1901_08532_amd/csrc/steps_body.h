@@ -126,8 +126,8 @@ __device__ __forceinline__ void correct_vals(const h6_state &st, int i, const do
     if (lev_crit > lev_old) {
         lev_new = lev_crit;
     } else if (lev_crit < lev_old) {
-        const int64_t two_old = dt_old << 1;
-        if (t_next % two_old == 0) lev_new = lev_old - 1;
+        const int64_t two_old = dt_old << 1;  // a power of two
+        if ((t_next & (two_old - 1)) == 0) lev_new = lev_old - 1;
     }
     if (lev_new > lev_max) {
         atomicOr(flags, kFlagDtMin);
