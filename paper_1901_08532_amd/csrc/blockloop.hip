@@ -216,37 +216,48 @@ __device__ __forceinline__ int fin_workers(int n_act, int split) {
 // LDS; d->cnt is written by the caller), with blocks / particle_steps the
 // totals so far: next block time, active levels and count, rank offsets,
 // evaluation shape; n_act = 0 and done = 1 once t_next would pass t_end.
-// One thread; reads only LDS and writes d.
+// One wave (all 64 lanes call it), lane L for level L: a wave minimum gives
+// t_next, a ballot the occupied levels, a suffix scan the rank offsets.
 __device__ void plan_block(const LoopArgs &A, LoopDesc *d, const int *cnt, int64_t t_cur,
                            uint64_t sel, int64_t blocks, int64_t psteps, int64_t seq_next) {
+    static_assert(kLevels <= 64, "one lane per level");
+    const int L = threadIdx.x & 63;
+    const bool listed = L >= A.lev_lo && L < A.lev_lo + A.nl;
+    const int c = listed ? cnt[L] : 0;
+    // next multiple of 2^(40 - L) ticks after t_cur (t_cur >= 0)
     int64_t tn = INT64_MAX;
-    int lv_hi = -1;
-    for (int L = A.lev_lo; L < A.lev_lo + A.nl; ++L) {
-        if (cnt[L] > 0) {
-            // next multiple of 2^(40 - L) ticks after t_cur (t_cur >= 0)
-            const int sh = kTickBits - L;
-            const int64_t cand = ((t_cur >> sh) + 1) << sh;
-            tn = cand < tn ? cand : tn;
-            lv_hi = L;
-        }
+    if (c > 0) {
+        const int sh = kTickBits - L;
+        tn = ((t_cur >> sh) + 1) << sh;
     }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int64_t o = __shfl_xor(tn, off, 64);
+        tn = o < tn ? o : tn;
+    }
+    const unsigned long long occ = __ballot(c > 0);
+    const int lv_hi = occ ? 63 - __builtin_clzll(occ) : -1;
+    const bool done = lv_hi < 0 || tn > A.t_end;
+    int L0 = done ? lv_hi : kTickBits - __builtin_ctzll((unsigned long long)tn);
+    if (!done && L0 < A.lev_lo) L0 = A.lev_lo;
+    // ranks run over the active levels from the highest down
+    const int mine = (!done && L >= L0) ? c : 0;
+    int incl = mine;  // sum over levels >= L
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_down(incl, off, 64);
+        if (L + off < 64) incl += o;
+    }
+    const int n_act = __shfl(incl, 0, 64);
+    if (!done && L >= L0 && L <= lv_hi) d->off[L] = incl - mine;
+    if (L != 0) return;
     d->t_next = tn;
     d->lv_hi = lv_hi;
     d->sel = sel;
     d->invalid = 0;
-    int n_act = 0;
-    if (lv_hi < 0 || tn > A.t_end) {
-        d->done = 1;
-        d->L0 = lv_hi;
-    } else {
-        int L0 = kTickBits - __builtin_ctzll((unsigned long long)tn);
-        if (L0 < A.lev_lo) L0 = A.lev_lo;
-        for (int L = lv_hi; L >= L0; --L) {
-            d->off[L] = n_act;
-            n_act += cnt[L];
-        }
-        d->L0 = L0;
-        d->done = 0;
+    d->L0 = L0;
+    d->done = done ? 1 : 0;
+    if (!done) {
         launch_shape(d, A.n, n_act, A.eval_grid, A.pc_pairs);
         blocks += 1;
         psteps += n_act;
@@ -298,9 +309,10 @@ __device__ void plan_next(const LoopArgs &A, const LoopDesc *__restrict__ cur, c
         dn->cnt[L] = c;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t flip = 0;
-        for (int L = L0 > A.lev_lo ? L0 : A.lev_lo; L < A.lev_lo + A.nl; ++L) flip |= 1ull << L;
+    if (threadIdx.x < 64) {
+        // list buffers flip for the active levels [max(L0, lev_lo), lev_lo + nl)
+        const int lo = L0 > A.lev_lo ? L0 : A.lev_lo;
+        const uint64_t flip = ((1ull << (A.lev_lo + A.nl)) - 1ull) & ~((1ull << lo) - 1ull);
         plan_block(A, dn, s_cnt, cur->t_next, cur->sel ^ flip, cur->blocks, cur->particle_steps,
                    seq + 1);
     }
@@ -454,7 +466,7 @@ __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t s
         const bool valid = tid < nt;
         int id = 0, lev = 0;
         if (valid) id = rank_to_particle(A, &rt, k0 + tid);  // overlaps the slice loads
-        {
+        if (w * (64 / seg) < nt) {  // waves holding a target of the round
             // seg lanes per target (contiguous slices: coalesced loads), the
             // nine components' loads of four passes issued together, then a
             // fixed butterfly within the segment
@@ -480,11 +492,10 @@ __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t s
 #pragma unroll
                     for (int c = 0; c < 9; ++c) neumaier(s[c], comp[c], x[q][c]);
             }
+            seg_comp_sum_n<9>(s, comp, seg);
 #pragma unroll
-            for (int c = 0; c < 9; ++c) {
-                seg_comp_sum(s[c], comp[c], seg);
+            for (int c = 0; c < 9; ++c)
                 if (has && o == 0) fs[r * 9 + c] = s[c] + comp[c];
-            }
         }
         __syncthreads();
         if (valid) {
@@ -599,9 +610,9 @@ __global__ void k_bl_setup_plan(LoopArgs A) {
         scr->reb[L] = 0u;
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    scr->bad = 0u;
     if (invalid) {
+        if (threadIdx.x != 0) return;
+        scr->bad = 0u;
         d->sel = 0ull;
         d->blocks = 0;
         d->particle_steps = 0;
@@ -612,7 +623,8 @@ __global__ void k_bl_setup_plan(LoopArgs A) {
         if (A.nact_log) A.nact_log[0] = 0;
         return;
     }
-    plan_block(A, d, s_cnt, (int64_t)tmax, 0ull, 0, 0, 0);
+    if (threadIdx.x == 0) scr->bad = 0u;
+    if (threadIdx.x < 64) plan_block(A, d, s_cnt, (int64_t)tmax, 0ull, 0, 0, 0);
 }
 
 }  // namespace

@@ -54,20 +54,55 @@ __device__ __forceinline__ void wave_comp_sum(double &s, double &c) {
     }
 }
 
-// The same butterfly within aligned segments of seg lanes (seg a power of
-// two up to 64, uniform across the wave): every lane gets its segment's
-// total.
-__device__ __forceinline__ void seg_comp_sum(double &s, double &c, int seg) {
-    const int lane = threadIdx.x & 63;
-    for (int off = seg >> 1; off >= 1; off >>= 1) {
-        const double s2 = __shfl_xor(s, off, 64);
-        const double c2 = __shfl_xor(c, off, 64);
-        double a = (lane & off) ? s2 : s, ac = (lane & off) ? c2 : c;
-        const double b = (lane & off) ? s : s2, bc = (lane & off) ? c : c2;
+// A double moved across lanes by a DPP lane pattern (both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// One butterfly stage for NV compensated pairs: every lane merges its value
+// with its partner's (partner value from DPP pattern CTRL, or from the lane
+// at XOR distance `off` when CTRL < 0), the lower group's value first.
+template <int NV, int CTRL>
+__device__ __forceinline__ void comp_stage(double *s, double *c, bool upper, int off) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double s2, c2;
+        if constexpr (CTRL >= 0) {
+            s2 = dpp_f64<CTRL>(s[q]);
+            c2 = dpp_f64<CTRL>(c[q]);
+        } else {
+            s2 = __shfl_xor(s[q], off, 64);
+            c2 = __shfl_xor(c[q], off, 64);
+        }
+        double a = upper ? s2 : s[q], ac = upper ? c2 : c[q];
+        const double b = upper ? s[q] : s2, bc = upper ? c[q] : c2;
         comp_merge(a, ac, b, bc);
-        s = a;
-        c = ac;
+        s[q] = a;
+        c[q] = ac;
     }
+}
+
+// The butterfly for NV compensated pairs at once (stage by stage, so the NV
+// exchanges of a stage are independent), within aligned segments of seg
+// lanes (seg a power of two up to 64, uniform across the wave): every lane
+// gets its segment's totals, the same in every lane and on every run.
+// Stages pair lane groups of 1, 2, 4, 8, 16, 32 lanes. The first four stay
+// within 16-lane rows and use DPP moves: quad permutations for the first
+// two, then the half-row and row mirrors, which pair the two halves of each
+// group of 8 (then 16) lanes; after the earlier stages every lane of a half
+// holds the same value, so a mirror partner is as good as the XOR one.
+template <int NV>
+__device__ __forceinline__ void seg_comp_sum_n(double *s, double *c, int seg) {
+    const int lane = threadIdx.x & 63;
+    if (seg >= 2) comp_stage<NV, 0xB1>(s, c, (lane & 1) != 0, 1);    // quad_perm [1,0,3,2]
+    if (seg >= 4) comp_stage<NV, 0x4E>(s, c, (lane & 2) != 0, 2);    // quad_perm [2,3,0,1]
+    if (seg >= 8) comp_stage<NV, 0x141>(s, c, (lane & 4) != 0, 4);   // row_half_mirror
+    if (seg >= 16) comp_stage<NV, 0x140>(s, c, (lane & 8) != 0, 8);  // row_mirror
+    if (seg >= 32) comp_stage<NV, -1>(s, c, (lane & 16) != 0, 16);
+    if (seg >= 64) comp_stage<NV, -1>(s, c, (lane & 32) != 0, 32);
 }
 
 }  // namespace h6

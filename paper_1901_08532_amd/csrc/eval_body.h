@@ -266,15 +266,20 @@ __device__ __forceinline__ void eval_tile_body(const SRC &S, int n, int n_act, d
 
 // Evaluation for small active sets (order 2): the lanes of a wave run over
 // sources (coalesced global loads, no LDS), each wave serving TPW targets
-// whose predicted state is wave-uniform; per-lane sums are flushed into
-// compensated pairs every kSmallFlush sources and combined across lanes by
-// a fixed butterfly. Grid: (one wave per TPW targets) x (source slices).
-constexpr int kSmallFlush = 16;
+// whose predicted state is wave-uniform. Each pass takes kSmallPass sources
+// per lane, their loads issued together (sources past the slice end are the
+// far massless padding); per-lane sums are flushed into compensated pairs
+// every kSmallFlush passes and combined across lanes by a fixed butterfly,
+// all 9 * TPW sums stage by stage. Grid: (one wave per TPW targets) x
+// (source slices).
+constexpr int kSmallPass = 4;
+constexpr int kSmallFlush = 4;
 
 template <int TPW, bool SKIPSELF, class SRC>
 __device__ __forceinline__ void eval_small_body(const SRC &S, int n, int n_act, double eps2,
                                                 int slice_len, const OutPtrs &out,
                                                 int64_t slice_stride, int wave, int sl) {
+    constexpr int PASS = TPW == 1 ? kSmallPass : kSmallPass / 2;  // register budget
     const int lane = threadIdx.x & 63;
     double xi[TPW][3], vi[TPW][3], ai[TPW][3];
     int pid[TPW];
@@ -295,29 +300,46 @@ __device__ __forceinline__ void eval_small_body(const SRC &S, int n, int n_act, 
 
     const int jb = sl * slice_len;
     const int je = min(n, jb + slice_len);
-    int since_flush = 0;
-    for (int j = jb + lane; j < je; j += 64) {
-        double xs[3], vs[3], as[3], jd[3];
-        S.template get<2>(j, xs, vs, as, jd);
-        const double xj0 = xs[0], xj1 = xs[1], xj2 = xs[2];
-        const double vj0 = vs[0], vj1 = vs[1], vj2 = vs[2];
-        const double aj0 = as[0], aj1 = as[1], aj2 = as[2];
-        const double mj = S.mass(j);
+    int passes = 0;
+    for (int jp = jb; jp < je; jp += PASS * 64) {
+        double xs[PASS][3], vs[PASS][3], as[PASS][3], ms[PASS];
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) {
-            const double dx = xj0 - xi[t][0], dy = xj1 - xi[t][1], dz = xj2 - xi[t][2];
-            double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
-            double m_eff = mj;
-            if (SKIPSELF) {
-                const bool self = j == pid[t];
-                r2 = self ? 1.0 : r2;
-                m_eff = self ? 0.0 : mj;
+        for (int u = 0; u < PASS; ++u) {
+            const int j = jp + u * 64 + lane;
+            if (j < je) {
+                double jd[3];
+                S.template get<2>(j, xs[u], vs[u], as[u], jd);
+                ms[u] = S.mass(j);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    xs[u][c] = kPadPos;
+                    vs[u][c] = as[u][c] = 0.0;
+                }
+                ms[u] = 0.0;
             }
-            pair_acc2(dx, dy, dz, vj0 - vi[t][0], vj1 - vi[t][1], vj2 - vi[t][2], aj0 - ai[t][0],
-                      aj1 - ai[t][1], aj2 - ai[t][2], r2, m_eff, acc[t]);
         }
-        if (++since_flush == kSmallFlush) {
-            since_flush = 0;
+#pragma unroll
+        for (int u = 0; u < PASS; ++u) {
+            const int j = jp + u * 64 + lane;
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const double dx = xs[u][0] - xi[t][0], dy = xs[u][1] - xi[t][1],
+                             dz = xs[u][2] - xi[t][2];
+                double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
+                double m_eff = ms[u];
+                if (SKIPSELF) {
+                    const bool self = j == pid[t];
+                    r2 = self ? 1.0 : r2;
+                    m_eff = self ? 0.0 : m_eff;
+                }
+                pair_acc2(dx, dy, dz, vs[u][0] - vi[t][0], vs[u][1] - vi[t][1],
+                          vs[u][2] - vi[t][2], as[u][0] - ai[t][0], as[u][1] - ai[t][1],
+                          as[u][2] - ai[t][2], r2, m_eff, acc[t]);
+            }
+        }
+        if (++passes == kSmallFlush) {
+            passes = 0;
 #pragma unroll
             for (int t = 0; t < TPW; ++t)
 #pragma unroll
@@ -327,17 +349,24 @@ __device__ __forceinline__ void eval_small_body(const SRC &S, int n, int n_act, 
                 }
         }
     }
-    const int64_t soff = (int64_t)sl * slice_stride;
+    double sv[TPW * 9], cv[TPW * 9];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) {
+    for (int t = 0; t < TPW; ++t)
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             two_sum_into(hi[t][q], lo[t][q], acc[t][q]);
-            double sv = hi[t][q], cv = lo[t][q];
-            wave_comp_sum(sv, cv);
-            const int k = wave * TPW + t;
-            if (lane == 0 && k < n_act) out.p[q][soff + k * out.kstride] = sv + cv;
+            sv[t * 9 + q] = hi[t][q];
+            cv[t * 9 + q] = lo[t][q];
         }
+    seg_comp_sum_n<TPW * 9>(sv, cv, 64);
+    const int64_t soff = (int64_t)sl * slice_stride;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int k = wave * TPW + t;
+        if (lane == 0 && k < n_act)
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+                out.p[q][soff + k * out.kstride] = sv[t * 9 + q] + cv[t * 9 + q];
     }
 }
 

@@ -162,12 +162,16 @@ __device__ __forceinline__ void mixed_tile_body(const SRC &S, int n, int n_act, 
 }
 
 // Small active sets: lanes over sources, TPW targets per wave (as the FP64
-// source-parallel kernel), FP32 pair arithmetic, FP32 partial sums over
+// source-parallel kernel, passes of kPassM sources per lane with their
+// loads issued together), FP32 pair arithmetic, FP32 partial sums over
 // kChunk sources per lane flushed into compensated FP64 pairs.
+constexpr int kPassM = 4;
+
 template <int TPW, bool SKIPSELF, class SRC>
 __device__ __forceinline__ void mixed_small_body(const SRC &S, int n, int n_act, double eps2,
                                                  int slice_len, const OutPtrs &out,
                                                  int64_t slice_stride, int wave, int sl) {
+    static_assert(kChunk % kPassM == 0, "flush on pass boundaries");
     const int lane = threadIdx.x & 63;
     const float eps2f = (float)eps2;
     double xi[TPW][3], vi[TPW][3];
@@ -196,29 +200,50 @@ __device__ __forceinline__ void mixed_small_body(const SRC &S, int n, int n_act,
     const int jb = sl * slice_len;
     const int je = min(n, jb + slice_len);
     int since_flush = 0;
-    for (int j = jb + lane; j < je; j += 64) {
-        double xs[3], vs[3], as[3], jd[3];
-        S.template get<2>(j, xs, vs, as, jd);
-        const double xj0 = xs[0], xj1 = xs[1], xj2 = xs[2];
-        const double vj0 = vs[0], vj1 = vs[1], vj2 = vs[2];
-        const float aj0 = (float)as[0], aj1 = (float)as[1], aj2 = (float)as[2];
-        const float mj = (float)S.mass(j);
+    for (int jp = jb; jp < je; jp += kPassM * 64) {
+        double xs[kPassM][3], vs[kPassM][3];
+        float as[kPassM][3], ms[kPassM];
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) {
-            const float dx = (float)(xj0 - xi[t][0]), dy = (float)(xj1 - xi[t][1]),
-                        dz = (float)(xj2 - xi[t][2]);
-            float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2f)));
-            float m_eff = mj;
-            if (SKIPSELF) {
-                const bool self = j == pid[t];
-                r2 = self ? 1.0f : r2;
-                m_eff = self ? 0.0f : mj;
+        for (int u = 0; u < kPassM; ++u) {
+            const int j = jp + u * 64 + lane;
+            if (j < je) {
+                double ad[3], jd[3];
+                S.template get<2>(j, xs[u], vs[u], ad, jd);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) as[u][c] = (float)ad[c];
+                ms[u] = (float)S.mass(j);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    xs[u][c] = kPadPosMixed;
+                    vs[u][c] = 0.0;
+                    as[u][c] = 0.0f;
+                }
+                ms[u] = 0.0f;
             }
-            pair_acc2_f32(dx, dy, dz, (float)(vj0 - vi[t][0]), (float)(vj1 - vi[t][1]),
-                          (float)(vj2 - vi[t][2]), aj0 - ai[t][0], aj1 - ai[t][1], aj2 - ai[t][2],
-                          r2, m_eff, acc32[t]);
         }
-        if (++since_flush == kChunk) {
+#pragma unroll
+        for (int u = 0; u < kPassM; ++u) {
+            const int j = jp + u * 64 + lane;
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const float dx = (float)(xs[u][0] - xi[t][0]), dy = (float)(xs[u][1] - xi[t][1]),
+                            dz = (float)(xs[u][2] - xi[t][2]);
+                float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2f)));
+                float m_eff = ms[u];
+                if (SKIPSELF) {
+                    const bool self = j == pid[t];
+                    r2 = self ? 1.0f : r2;
+                    m_eff = self ? 0.0f : m_eff;
+                }
+                pair_acc2_f32(dx, dy, dz, (float)(vs[u][0] - vi[t][0]),
+                              (float)(vs[u][1] - vi[t][1]), (float)(vs[u][2] - vi[t][2]),
+                              as[u][0] - ai[t][0], as[u][1] - ai[t][1], as[u][2] - ai[t][2], r2,
+                              m_eff, acc32[t]);
+            }
+        }
+        since_flush += kPassM;
+        if (since_flush == kChunk) {
             since_flush = 0;
 #pragma unroll
             for (int t = 0; t < TPW; ++t)
@@ -229,17 +254,24 @@ __device__ __forceinline__ void mixed_small_body(const SRC &S, int n, int n_act,
                 }
         }
     }
-    const int64_t soff = (int64_t)sl * slice_stride;
+    double sv[TPW * 9], cv[TPW * 9];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) {
+    for (int t = 0; t < TPW; ++t)
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             two_sum_into(hi[t][q], lo[t][q], (double)acc32[t][q]);
-            double sv = hi[t][q], cv = lo[t][q];
-            wave_comp_sum(sv, cv);
-            const int k = wave * TPW + t;
-            if (lane == 0 && k < n_act) out.p[q][soff + k * out.kstride] = sv + cv;
+            sv[t * 9 + q] = hi[t][q];
+            cv[t * 9 + q] = lo[t][q];
         }
+    seg_comp_sum_n<TPW * 9>(sv, cv, 64);
+    const int64_t soff = (int64_t)sl * slice_stride;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int k = wave * TPW + t;
+        if (lane == 0 && k < n_act)
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+                out.p[q][soff + k * out.kstride] = sv[t * 9 + q] + cv[t * 9 + q];
     }
 }
 
