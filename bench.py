@@ -21,6 +21,10 @@ vector peak.
 cpu_baseline: the FP64 CPU oracle, timed on a bounded sample of the same
 workload (its a/j/s evaluation of sampled targets against all sources).
 
+--workload adjoint measures the differentiable shared-step path instead
+(loss and full gradient through 64 shared steps, N = 16384); its JSON line
+names its own metric.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 
@@ -98,14 +102,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=65536)
-    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--n", type=int, default=None,
+                    help="particles (default 65536; 16384 for the adjoint workload)")
+    ap.add_argument("--seed", type=int, default=None,
+                    help="initial-condition seed (default 2; 4 for the adjoint workload)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
-    ap.add_argument("--workload", choices=("plummer", "plummer-imf", "two-clusters"),
+    ap.add_argument("--workload", choices=("plummer", "plummer-imf", "two-clusters", "adjoint"),
                     default="plummer",
                     help="equal-mass Plummer sphere; Plummer with dN/dm ~ m^-2.35 masses "
                          "(mass seed 10*seed+seed); two Plummer spheres of n/2 on a head-on "
-                         "approach (seeds seed, 10*seed+seed)")
+                         "approach (seeds seed, 10*seed+seed); adjoint: gradient of a loss on "
+                         "the final positions of 64 shared steps (one step = forward + backward)")
+    ap.add_argument("--accuracy-targets", type=int, default=64,
+                    help="sampled targets of the final state checked against the FP64 oracle")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -119,6 +128,11 @@ def main():
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "adjoint":
+        return run_adjoint(args)
+    args.n = 65536 if args.n is None else args.n
+    args.seed = 2 if args.seed is None else args.seed
 
     import numpy as np
     import torch
@@ -235,7 +249,7 @@ def main():
     import oracle
 
     rng = np.random.Generator(np.random.PCG64(7))
-    idx = np.sort(rng.choice(n, 64, replace=False))
+    idx = np.sort(rng.choice(n, min(n, args.accuracy_targets), replace=False))
     F = torch.empty((9, n), dtype=torch.float64, device="cuda")
     P = sysg.S[0:9].contiguous()
     act = torch.from_numpy(idx.astype(np.int32)).cuda()
@@ -295,12 +309,177 @@ def main():
         "pct_fp64_vector_peak": 100.0 * value * FLOPS_PER_INTERACTION / (FP64_PEAK_TFLOPS * 1e12),
         "pct_fp32_vector_peak": 100.0 * value * FLOPS_PER_INTERACTION / (FP32_PEAK_TFLOPS * 1e12),
         "blocks": blocks,
+        "block_us_avg": 1e6 * wall / max(1, blocks),
         "particle_steps": psteps,
         "interactions": inter,
         "eval_kernel_share_of_wall": 1e-3 * eval_ms / wall if wall > 0 else None,
         "eval_by_active_set": by_active,
         "energy_rel_err_max": drift,
         "accuracy": acc,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+VJP_COUNTER_FILE = os.path.join(ROOT, "profiles", "eval_vjp_valu_counters.md")
+ADJ_METRIC = "pair-sum passes x N^2 per second, forward sums and their vector-Jacobian products"
+
+
+def _vjp_flops_per_pair():
+    """Executed FP64 flops per pair of the evaluation VJP kernel (FMA 2,
+    ADD/MUL/TRANS 1) from the committed counter summary, or None."""
+    if not os.path.exists(VJP_COUNTER_FILE):
+        return None
+    for line in open(VJP_COUNTER_FILE):
+        if line.startswith("executed FP64 flops per interaction"):
+            return float(line.rsplit("=", 1)[1])
+    return None
+
+
+def run_adjoint(args):
+    """Adjoint workload: Plummer N = 16384, eps = 1e-3, start-up then 64
+    shared steps of 1/256 with a checkpoint every 8 steps; loss = sum of
+    squared distances of the final positions from perturbed targets. One
+    bench step is one loss evaluation plus its full gradient with respect to
+    the initial positions, velocities and masses (forward integration, then
+    the backward pass: segment replay from the checkpoints and the
+    hand-written transposes). value counts, per bench step, the pair-sum
+    passes of the method (2 start-up passes + one per shared step) and their
+    VJPs (one each), times N^2; the replay of the forward steps inside the
+    backward pass is not counted."""
+    import numpy as np
+    import torch
+
+    from paper_1901_08532_amd import h6, ics
+    from paper_1901_08532_amd.adjoint import hermite_shared_run
+
+    n = 16384 if args.n is None else args.n
+    seed = 4 if args.seed is None else args.seed
+    eps, dt, nsteps, ckpt = 1e-3, 1.0 / 256, 64, 8
+    torch.cuda.set_device(0)
+    _log("inputs: adjoint plummer N=%d seed=%d" % (n, seed))
+    x, v, m = ics.plummer(n, seed)
+    rng = np.random.Generator(np.random.PCG64(10 * seed + seed))
+    xt = x + 0.01 * rng.normal(0, 1, (n, 3))
+    ctx = h6.Context(n, eps)
+    X0, V0, M0, XT = (torch.from_numpy(a).cuda() for a in (x, v, m, xt))
+
+    def one():
+        x0, v0, m0 = (a.clone().requires_grad_(True) for a in (X0, V0, M0))
+        xT = hermite_shared_run(x0, v0, m0, ctx, dt, nsteps, ckpt)
+        loss = ((xT - XT) ** 2).sum()
+        g = torch.autograd.grad(loss, (x0, v0, m0))
+        return loss.detach(), g
+
+    for w in range(args.warmup):
+        one()
+        torch.cuda.synchronize()
+        _log("warmup step %d done" % w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        loss, grads = one()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    passes = 2 * nsteps + 4
+    value = args.steps * passes * float(n) * n / wall
+    _log("timed %d loss+gradient evaluations: %.3f s" % (args.steps, wall))
+    finite = all(bool(torch.isfinite(g).all()) for g in grads) and bool(torch.isfinite(loss))
+
+    # the evaluation and its VJP alone, on the predicted state of the first
+    # step, timed with events on the library's stream (torch's current one)
+    S = torch.zeros((18, n), dtype=torch.float64, device="cuda")
+    S[0:3] = X0.T
+    S[3:6] = V0.T
+    ctx.h6_init_forces(S, M0)
+    P = torch.empty((9, n), dtype=torch.float64, device="cuda")
+    ctx.h6_predict_dt(S, M0, dt, P)
+    F = torch.empty((9, n), dtype=torch.float64, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    CF = torch.randn((9, n), dtype=torch.float64, device="cuda", generator=gen)
+    CP = torch.empty((9, n), dtype=torch.float64, device="cuda")
+    gm = torch.zeros(n, dtype=torch.float64, device="cuda")
+    reps = 10
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    t_eval = timed(lambda: ctx.h6_evaluate(P, M0, None, n, h6.H6_FP64, F))
+    t_vjp = timed(lambda: ctx.h6_evaluate_vjp(P, M0, CF, CP, gm))
+    pairs = float(n) * n
+    fpp = _vjp_flops_per_pair()
+    achieved = fpp * pairs / t_vjp / 1e12 if fpp is not None else None
+    roofline = {
+        "bound": "alu",
+        "achieved": achieved,
+        "peak": FP64_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": achieved / FP64_PEAK_TFLOPS if achieved is not None else None,
+        "traffic": None,
+        "kernel": "k_eval_vjp<2, 128, false> + slice reduction (one h6_evaluate_vjp call)",
+        "flops_per_pair": fpp,
+        "flops_convention": "executed FP64 flops per pair from the VALU counters (FMA 2, ADD/MUL/TRANS 1)",
+        "avg_call_us": 1e6 * t_vjp,
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the autograd CPU reference on a small system of the same kind: its
+        # all-pairs tensors and graph do not fit N = 16384
+        import oracle.adjoint_ref as ar
+
+        n_c = 256
+        xc, vc, mc = ics.plummer(n_c, seed)
+        xtc = xc + 0.01 * rng.normal(0, 1, (n_c, 3))
+        tp = time.perf_counter()
+        ar.loss_and_grad(xc, vc, mc, xtc, eps * eps, dt, 2)
+        tp = time.perf_counter() - tp
+        steps_c = int(max(2, min(nsteps, 2 * args.cpu_seconds / max(tp, 1e-6))))
+        tc = time.perf_counter()
+        ar.loss_and_grad(xc, vc, mc, xtc, eps * eps, dt, steps_c)
+        tc = time.perf_counter() - tc
+        cpu = {
+            "value": (2 * steps_c + 4) * float(n_c) * n_c / tc,
+            "unit": "pair-sum passes x N^2 per second",
+            "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": "FP64 autograd reference, loss and gradient of Plummer N=%d through %d shared "
+                      "steps of 1/256 (%.1f s)" % (n_c, steps_c, tc),
+        }
+        _log("cpu baseline: %.3e on %d threads" % (cpu["value"], cpu["cores"]))
+
+    out = {
+        "metric": ADJ_METRIC,
+        "value": value,
+        "unit": "pair-sum passes x N^2 per second",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / max(1, args.steps),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "adjoint_plummer_n%d_eps1e-3_64_shared_steps_dt1/256_checkpoint8" % n,
+            "n": n, "eps": eps, "dt": dt, "shared_steps": nsteps, "checkpoint": ckpt,
+            "seed": seed, "passes_per_step": passes,
+        },
+        "gradient_finite": finite,
+        "eval_call_us": 1e6 * t_eval,
+        "vjp_call_us": 1e6 * t_vjp,
+        "vjp_over_eval_time": t_vjp / t_eval,
+        "eval_pct_fp64_peak": 100.0 * FLOPS_PER_INTERACTION * pairs / t_eval / (FP64_PEAK_TFLOPS * 1e12),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
