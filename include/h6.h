@@ -55,10 +55,15 @@ enum {
     H6_ENONFINITE = -6  /* a corrected quantity was not finite */
 };
 
-/* Evaluation arithmetic (Sec. 3 item 6). */
+/* Evaluation arithmetic (Sec. 3 item 6: double, an extended type of about
+ * 48 significand bits with single-precision exponents, or single). The
+ * predictor, corrector and step rule are FP64 in every case. */
 enum {
     H6_FP64 = 0,  /* all pair arithmetic and sums in IEEE double */
-    H6_MIXED = 1  /* double differences and accumulators, float pair math */
+    H6_MIXED = 1, /* double differences and accumulators, float pair math */
+    H6_EX = 2,    /* double-single ("float-float") pair arithmetic and
+                     per-slice sums, float operations only */
+    H6_SP = 3     /* single-precision pair arithmetic and per-slice sums */
 };
 
 typedef struct h6_ctx_s *h6_ctx;
@@ -88,7 +93,8 @@ typedef struct {
     double eta;    /* accuracy parameter of the 6th-order criterion */
     int lev_min;   /* largest step 2^-lev_min */
     int lev_max;   /* smallest step 2^-lev_max (below: H6_EDTMIN) */
-    int precision; /* H6_FP64 or H6_MIXED for the evaluation */
+    int precision; /* H6_FP64, H6_MIXED, H6_EX or H6_SP for the evaluation;
+                      H6_EX and H6_SP always run the host loop */
     int host_loop; /* h6_run_blocks: 0 device-resident loop, 1 one host
                       round trip per block (h6_block_step repeated) */
 } h6_params;
@@ -148,7 +154,9 @@ int h6_predict_dt(h6_ctx ctx, const h6_state *st, int64_t n, double dt,
  * k < n_act, particle i = active[k] (active may be NULL: i = k), the sums
  * over every source j != i of the softened acceleration, jerk and snap
  * from the predicted x, v, a and masses m of all n particles. Results go to
- * out at index k. precision is H6_FP64 or H6_MIXED. n_act == 0 is a no-op.
+ * out at index k. precision is H6_FP64, H6_MIXED, H6_EX or H6_SP (see the
+ * enum above; EX and SP accumulate per source slice in their own arithmetic,
+ * and the slices are combined in FP64). n_act == 0 is a no-op.
  * Errors: H6_EINVAL (null pointer, n < 1, n > n_max, n_act < 0 or
  * n_act > n_max, bad precision). Active indices must lie in [0, n); they
  * are not checked on the device.
@@ -328,7 +336,7 @@ typedef struct {
     int order;      /* 2: per-step a/j/s; 1, 3: start-up passes */
     int kind;       /* 0: LDS-tiled kernel; 1: source-parallel small-set kernel */
     int block, ipl; /* launch shape of the instantiation */
-    int precision;  /* H6_FP64 or H6_MIXED */
+    int precision;  /* H6_FP64, H6_MIXED, H6_EX or H6_SP */
     int nact_log2;  /* bin: floor(log2(n_act)) of the launches in this record */
     int64_t launches;
     double interactions; /* sum of n_act * n over the launches */

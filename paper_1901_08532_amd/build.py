@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libh6.so")
-SOURCES = ["eval.hip", "eval_mixed.hip", "adjoint.hip", "steps.hip", "blockloop.hip", "api.hip"]
+SOURCES = ["eval.hip", "eval_mixed.hip", "eval_ex.hip", "adjoint.hip", "steps.hip", "blockloop.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 CFLAGS = [

@@ -62,10 +62,12 @@ bool force_ok(const h6_force *f) {
     return true;
 }
 
+bool precision_ok(int p) { return p == H6_FP64 || p == H6_MIXED || p == H6_EX || p == H6_SP; }
+
 bool params_ok(const h6_params *p) {
     return p && std::isfinite(p->eta) && p->eta > 0.0 && p->lev_min >= 0 &&
            p->lev_max >= p->lev_min && p->lev_max <= kTickBits &&
-           (p->precision == H6_FP64 || p->precision == H6_MIXED) &&
+           precision_ok(p->precision) &&
            (p->host_loop == 0 || p->host_loop == 1);
 }
 
@@ -339,7 +341,7 @@ int h6_evaluate(h6_ctx ctx, const h6_pred *src, const double *m, int64_t n, cons
     if (int rc = check_n(ctx, n)) return rc;
     if (n_act < 0 || n_act > ctx->n_max) return fail_arg(ctx, "n_act out of range");
     if (!active && n_act > n) return fail_arg(ctx, "n_act > n without an active list");
-    if (precision != H6_FP64 && precision != H6_MIXED) return fail_arg(ctx, "bad precision");
+    if (!precision_ok(precision)) return fail_arg(ctx, "bad precision");
     if (n_act == 0) return H6_OK;
     H6_TRY(ctx,
            launch_eval(ctx, 2, precision, src_from_pred(src, m), (int)n, active, (int)n_act,
@@ -579,7 +581,9 @@ int h6_run_blocks(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred, cons
         return fail_arg(ctx, "null pointer");
     if (!params_ok(prm)) return fail_arg(ctx, "bad step parameters");
     if (int rc = check_n(ctx, n)) return rc;
-    if (prm->host_loop) return run_blocks_host(ctx, st, n, pred, f, active, prm, t_end, stats);
+    // the device loop carries the FP64 and mixed kernels only
+    if (prm->host_loop || prm->precision == H6_EX || prm->precision == H6_SP)
+        return run_blocks_host(ctx, st, n, pred, f, active, prm, t_end, stats);
     return run_blocks_device(ctx, st, n, pred, f, active, prm, t_end, stats);
 }
 
@@ -589,7 +593,7 @@ int h6_shared_steps(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred, co
     if (!state_ok(st, false) || !pred_ok(pred) || !force_ok(f)) return fail_arg(ctx, "null pointer");
     if (int rc = check_n(ctx, n)) return rc;
     if (!std::isfinite(dt) || dt <= 0.0 || nsteps < 0) return fail_arg(ctx, "bad dt or step count");
-    if (precision != H6_FP64 && precision != H6_MIXED) return fail_arg(ctx, "bad precision");
+    if (!precision_ok(precision)) return fail_arg(ctx, "bad precision");
     for (int64_t k = 0; k < nsteps; ++k) {
         H6_TRY(ctx, launch_predict(ctx, st, (int)n, 0, dt, true, pred), "predict");
         H6_TRY(ctx,

@@ -205,8 +205,21 @@ int balanced_split(h6_ctx ctx, int waves_per_simd, int block, int n, int blocks_
 }
 
 EvalConfig choose_eval_config(h6_ctx ctx, int order, int precision, int n, int n_act) {
-    (void)precision;
     EvalConfig cfg;
+    if (order == 2 && (precision == H6_EX || precision == H6_SP)) {
+        cfg.kind = 0;
+        cfg.block = kExtBlock;
+        cfg.ipl = 1;
+        // slices down to one tile: a double-single pair costs ~20x an FP64
+        // one, so even small active sets need many workgroups
+        const int blocks_i = ceil_div(n_act, kExtBlock);
+        int split = std::max(1, ceil_div(4 * ctx->n_cu, blocks_i));
+        split = std::min(split, ceil_div(n, kExtBlock));
+        const int64_t cap_split = ctx->partial_cap / ((int64_t)9 * n_act);
+        if (split > cap_split) split = (int)(cap_split < 1 ? 1 : cap_split);
+        cfg.n_split = split < 1 ? 1 : split;
+        return cfg;
+    }
     const int small_max = ctx->cfg_small >= 0 ? ctx->cfg_small : kDefaultSmallMax;
     if (order == 2 && n_act <= small_max) {
         // source-parallel kernel: one wave per TPW targets
@@ -287,7 +300,10 @@ hipError_t launch_eval(h6_ctx ctx, int order, int precision, const SrcPtrs &src,
         if (pe != hipSuccess) return pe;
     }
     hipError_t e;
-    if (order == 2 && precision == H6_MIXED) {
+    if (order == 2 && (precision == H6_EX || precision == H6_SP)) {
+        e = dispatch_ext(precision, skipself, grid, ctx->stream, src, active, n, n_act, ctx->eps2,
+                         slice_len, dst, slice_stride);
+    } else if (order == 2 && precision == H6_MIXED) {
         dim3 g = cfg.kind == 1 ? dim3(ceil_div(n_act, cfg.ipl), cfg.n_split) : grid;
         e = dispatch_mixed(cfg, skipself, g, ctx->stream, src, active, n, n_act, ctx->eps2,
                            slice_len, dst, slice_stride);

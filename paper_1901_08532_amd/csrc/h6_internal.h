@@ -37,6 +37,7 @@ struct OutPtrs {
 // ---- device-resident block loop (blockloop.hip)
 constexpr int kLevels = kTickBits + 1;  // levels 0..40: step 2^-level
 constexpr int kSmall2Max = 48;          // largest active set of the source-parallel kinds
+constexpr int kExtBlock = 64;           // workgroup of the EX and SP kernels (one target per lane)
 
 // Plan of one block, written by the plan of the block before (double
 // buffered by block parity) and read by the kernels of the block.
@@ -158,6 +159,11 @@ int balanced_split(h6_ctx ctx, int waves_per_simd, int block, int n, int blocks_
 hipError_t dispatch_mixed(const EvalConfig &cfg, bool skipself, dim3 grid, hipStream_t st,
                           const SrcPtrs &src, const int32_t *active, int n, int n_act, double eps2,
                           int slice_len, const OutPtrs &out, int64_t slice_stride);
+// Double-single (H6_EX) and single-precision (H6_SP) order-2 kernels
+// (eval_ex.hip): kExtBlock threads, one target per lane.
+hipError_t dispatch_ext(int precision, bool skipself, dim3 grid, hipStream_t st, const SrcPtrs &src,
+                        const int32_t *active, int n, int n_act, double eps2, int slice_len,
+                        const OutPtrs &out, int64_t slice_stride);
 
 hipError_t launch_predict(h6_ctx ctx, const h6_state *st, int n, int64_t t_tick, double dt,
                           bool shared, const h6_pred *out);

@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libh6.so")
 
 H6_OK, H6_EINVAL, H6_ENOMEM, H6_EHIP, H6_ESTATE, H6_EDTMIN, H6_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
-H6_FP64, H6_MIXED = 0, 1
+H6_FP64, H6_MIXED, H6_EX, H6_SP = 0, 1, 2, 3
 TICK_BITS = 40
 TICKS_PER_UNIT = 1 << TICK_BITS
 
