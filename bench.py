@@ -425,7 +425,7 @@ def run_adjoint(args):
         "unit": "TFLOP/s",
         "frac": achieved / FP64_PEAK_TFLOPS if achieved is not None else None,
         "traffic": None,
-        "kernel": "k_eval_vjp<2, 128, false> + slice reduction (one h6_evaluate_vjp call)",
+        "kernel": "k_eval_vjp<2, 128, 0> + slice reduction (one h6_evaluate_vjp call)",
         "flops_per_pair": fpp,
         "flops_convention": "executed FP64 flops per pair from the VALU counters (FMA 2, ADD/MUL/TRANS 1)",
         "avg_call_us": 1e6 * t_vjp,

@@ -325,6 +325,61 @@ int h6_init_forces_vjp(h6_ctx ctx, const h6_state *st, int64_t n,
                        h6_state *cot);
 
 /*
+ * ---- Adjoint of the block-step path (levels frozen) ----
+ * The step of every particle is treated as a constant: gradients flow
+ * through the predictor, evaluation and corrector of each block along the
+ * block sequence the forward run took, not through the choice of steps.
+ */
+
+/*
+ * VJP of h6_evaluate over an active set (the evaluation of one block): the
+ * targets are the n_act particles active[0..n_act), cot holds the
+ * cotangents of their evaluated a, j, s by rank (length n_act), and the
+ * sources are all n particles (predicted src, masses m). ADDS the
+ * cotangents of the predicted x, v, a of every particle to grad_src and of
+ * the masses to grad_m (both length n). Work: about 2 n_act n pairs (each
+ * pair's source part over the active sources for every particle, then its
+ * target part over all sources for the active ones); self pairs skipped.
+ * Active entries must be distinct and in [0, n) (not checked on the
+ * device). n_act == 0 is a no-op. Errors: H6_EINVAL.
+ */
+int h6_evaluate_vjp_active(h6_ctx ctx, const h6_pred *src, const double *m, int64_t n,
+                           const int32_t *active, int64_t n_act, const h6_force *cot,
+                           const h6_pred *grad_src, double *grad_m);
+
+/*
+ * Transpose of the block-step corrector (h6_correct) for the particles
+ * active[0..n_act), each over its own step dt_old[i] (ticks, the steps held
+ * before the block; length n). On entry cot holds the cotangents of the
+ * corrected state; on return, for the active particles, those of the state
+ * before the block (x, v, a, j, s; c set to 0, the old crackle entering
+ * only the predictor), and cot_force (by rank, length n_act) those of the
+ * evaluated a, j, s. Other particles' cotangents are left unchanged.
+ * cot->m, t, dt are not used. Errors: H6_EINVAL.
+ */
+int h6_correct_vjp(h6_ctx ctx, h6_state *cot, int64_t n, const int32_t *active,
+                   int64_t n_act, const int64_t *dt_old, const h6_force *cot_force);
+
+/*
+ * Transpose of h6_predict to time t_tick: ADDS to the state cotangents
+ * (x, v, a, j, s, c) the contribution of the cotangents cot_pred of the
+ * predicted x, v, a, each particle over its own interval t_tick - t_old[i]
+ * (ticks; t_old the particle times before the block, length n).
+ * Errors: H6_EINVAL.
+ */
+int h6_predict_vjp(h6_ctx ctx, h6_state *cot, int64_t n, const int64_t *t_old,
+                   int64_t t_tick, const h6_pred *cot_pred);
+
+/*
+ * Potential of every particle (Sec. 3 item 3 diagnostics, per particle):
+ * phi[i] = -sum_{j != i} m_j / sqrt(|x_j - x_i|^2 + eps^2), from st->x and
+ * st->m (other fields unused). The total potential energy is
+ * sum_i m_i phi[i] / 2, and the derivative of the total energy with respect
+ * to m_i is |v_i|^2 / 2 + phi[i]. Errors: H6_EINVAL.
+ */
+int h6_potential(h6_ctx ctx, const h6_state *st, int64_t n, double *phi);
+
+/*
  * Measurement hook: while enabled, HIP events bracket every a/j/s
  * evaluation kernel the context launches (on its stream), and the event
  * durations are accumulated per kernel instantiation and per power-of-two

@@ -76,6 +76,8 @@ def lib():
         L.orc_shared_steps.restype = C.c_int
         L.orc_energy.argtypes = [C.c_int64, dp, dp, dp, C.c_double, dp]
         L.orc_energy.restype = C.c_int
+        L.orc_potential.argtypes = [C.c_int64, dp, dp, C.c_double, dp]
+        L.orc_potential.restype = C.c_int
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = C.c_int
         _lib = L
@@ -256,6 +258,14 @@ class State:
 
     def energy(self):
         return energy(self.x, self.v, self.m, self.eps2)
+
+
+def potential(x, m, eps2):
+    """phi[i] = -sum_{j != i} m_j / sqrt(r_ij^2 + eps2), shape (n,)."""
+    x, m = _v(x), _v(m)
+    phi = np.zeros(x.shape[0])
+    lib().orc_potential(x.shape[0], _d(x), _d(m), float(eps2), _d(phi))
+    return phi
 
 
 def energy(x, v, m, eps2):

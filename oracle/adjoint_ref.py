@@ -82,6 +82,65 @@ def run(x0, v0, m, eps2, h, nsteps):
     return x, v, a, j, s, c
 
 
+TICK = 2.0 ** -40
+
+
+def block_schedule(x0, v0, m, eps2, t_end, eta=0.4, lev_min=4, lev_max=30, eta_s=0.1):
+    """The block sequence the C oracle takes from the start-up to t_end
+    (ticks): a list of (t_next, active indices, particle times before the
+    block, particle steps before the block). Used to unroll block_run."""
+    from . import State, next_block
+
+    st = State(x0, v0, m, eps2)
+    st.startup(eta_s, lev_min, lev_max)
+    sched = []
+    while True:
+        tn, act = next_block(st.t, st.dt)
+        if tn > t_end:
+            break
+        sched.append((tn, act.copy(), st.t.copy(), st.dt.copy()))
+        rc, _, _ = st.block_step(eta, lev_min, lev_max)
+        if rc < 0 and rc != -5:  # -5: a step clamped at 2^-lev_max (run continues)
+            raise ValueError("oracle block step failed (%d)" % rc)
+    return sched
+
+
+def block_run(x0, v0, m, eps2, schedule):
+    """Start-up, then the blocks of `schedule` with their steps held fixed:
+    per block, every particle predicted over its own interval to t_next,
+    a, j, s evaluated at the predicted states, and the active particles
+    corrected over their own steps. Returns the final (x, v, a, j, s, c)."""
+    a, j, s, c = startup(x0, v0, m, eps2)
+    x, v = x0, v0
+    n = x.shape[0]
+    for tn, act, t_old, dt_old in schedule:
+        d = torch.as_tensor((tn - t_old) * TICK, dtype=torch.float64)[:, None]
+        xp = x + d * v + d ** 2 / 2 * a + d ** 3 / 6 * j + d ** 4 / 24 * s + d ** 5 / 120 * c
+        vp = v + d * a + d ** 2 / 2 * j + d ** 3 / 6 * s + d ** 4 / 24 * c
+        ap = a + d * j + d ** 2 / 2 * s + d ** 3 / 6 * c
+        a1, j1, s1 = pair_sums(xp, vp, m, eps2, a=ap, order=2)
+        h = torch.as_tensor(dt_old * TICK, dtype=torch.float64)[:, None]
+        v1 = v + h / 2 * (a + a1) - h ** 2 / 10 * (j1 - j) + h ** 3 / 120 * (s + s1)
+        x1 = x + h / 2 * (v + v1) - h ** 2 / 10 * (a1 - a) + h ** 3 / 120 * (j + j1)
+        c1 = (60.0 * (a1 - a) - h * (24.0 * j + 36.0 * j1) + h ** 2 * (9.0 * s1 - 3.0 * s)) / h ** 3
+        mask = torch.zeros(n, dtype=torch.bool)
+        mask[torch.as_tensor(act, dtype=torch.int64)] = True
+        mk = mask[:, None]
+        x, v = torch.where(mk, x1, x), torch.where(mk, v1, v)
+        a, j, s, c = (torch.where(mk, new, old) for new, old in ((a1, a), (j1, j), (s1, s), (c1, c)))
+    return x, v, a, j, s, c
+
+
+def energy(x, v, m, eps2):
+    """Kinetic plus softened potential energy (pairs i < j), a 0-d tensor."""
+    n = x.shape[0]
+    r = x[None, :, :] - x[:, None, :]
+    R = ((r * r).sum(-1) + eps2) ** -0.5
+    iu = torch.triu_indices(n, n, offset=1)
+    pot = -(m[iu[0]] * m[iu[1]] * R[iu[0], iu[1]]).sum()
+    return 0.5 * (m * (v * v).sum(-1)).sum() + pot
+
+
 def loss_and_grad(x0, v0, m, x_target, eps2, h, nsteps):
     """Loss sum |x_T - x_target|^2 and its gradient w.r.t. (x0, v0, m)."""
     x0 = torch.as_tensor(x0, dtype=torch.float64).clone().requires_grad_(True)

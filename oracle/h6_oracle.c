@@ -627,3 +627,27 @@ int orc_energy(int64_t n, const double *x, const double *v, const double *m,
     free(phi);
     return 0;
 }
+
+/*
+ * Potential of each particle (the per-particle terms of the energy of
+ * Sec. 3 item 3): phi[i] = -sum_{j != i} m_j / sqrt(|x_j - x_i|^2 + eps^2),
+ * compensated. sum_i m_i phi[i] / 2 is the potential energy.
+ */
+int orc_potential(int64_t n, const double *x, const double *m, double eps2, double *phi)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < n; i++) {
+        csum p = {0.0, 0.0};
+        for (int64_t jj = 0; jj < n; jj++) {
+            if (jj == i)
+                continue;
+            double r[3];
+            for (int c = 0; c < 3; c++)
+                r[c] = x[3 * jj + c] - x[3 * i + c];
+            cs_add(&p, m[jj] / sqrt(dot3(r, r) + eps2));
+        }
+        phi[i] = -cs_val(&p);
+    }
+    return 0;
+}

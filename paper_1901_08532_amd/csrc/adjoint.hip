@@ -12,8 +12,8 @@
 //   mbar_k = -sum_j Q . g_j.
 // (dQ/d.)^T is applied by the hand reversal of the forward pair code:
 // the forward values of R^-3, alpha, beta, gamma, w, u, z are recomputed,
-// then their adjoints are accumulated in reverse order. The self pair has
-// m_k g_k - m_k g_k = 0 and Q = 0, so it contributes nothing.
+// then their adjoints are accumulated in reverse order. The self pair
+// (whose terms cancel in exact arithmetic) is excluded explicitly.
 //
 // Launch structure as the forward kernel: LDS tiles of source records,
 // one target per lane, source slices combined by the compensated slice
@@ -52,8 +52,8 @@ __device__ __forceinline__ double dot3(const double *p, const double *q) {
 }
 
 // Reverse-mode pair: accumulates (dQ/dr)^T gh into xb, (dQ/dv)^T gh into vb,
-// (dQ/da)^T gh into ab, (dQ/djr)^T gh into jb, and -Q . gj into mb.
-template <int ORDER>
+// (dQ/da)^T gh into ab, (dQ/djr)^T gh into jb, and (MASS) -Q . gj into mb.
+template <int ORDER, bool MASS = true>
 __device__ __forceinline__ void pair_vjp(const double *r, const double *v, const double *a,
                                          const double *jr, double r2, const double *gh,
                                          const double *gj, double *xb, double *vb, double *ab,
@@ -93,10 +93,12 @@ __device__ __forceinline__ void pair_vjp(const double *r, const double *v, const
     const double *Sj = ORDER == 2 ? gj + 6 : ORDER == 3 ? gj : zero3;
     const double *Cj = ORDER == 3 ? gj + 3 : zero3;
     // mass: -Q . g_j with Q = R^-3 (r, w, u, z) for (A, J, S, C)
-    double qg = dot3(r, Aj) + dot3(w, Jj);
-    if constexpr (ORDER >= 2) qg += dot3(u, Sj);
-    if constexpr (ORDER == 3) qg += dot3(z, Cj);
-    mb = fma(-q3, qg, mb);
+    if constexpr (MASS) {
+        double qg = dot3(r, Aj) + dot3(w, Jj);
+        if constexpr (ORDER >= 2) qg += dot3(u, Sj);
+        if constexpr (ORDER == 3) qg += dot3(z, Cj);
+        mb = fma(-q3, qg, mb);
+    }
     // ---- reverse sweep
     double q3b = dot3(Ab, r) + dot3(Jb, w);
     if constexpr (ORDER >= 2) q3b += dot3(Sb, u);
@@ -190,17 +192,35 @@ struct CotPtrs {
 
 constexpr double kPadPosVjp = 1.0e18;
 
-template <int ORDER, int BLOCK, bool SKIPSELF>
+// Which pairs and which half of each pair a launch covers. With the
+// cotangents g nonzero only on an active set (block steps), the pair sum
+// splits into a source half m_k g_j over the active sources j, for every
+// target k (with the mass term), and a target half -m_j g_k over all
+// sources, for the active targets k: 2 n_act n pairs instead of n^2.
+//   kAll:        targets 0..n-1 against sources 0..n-1, both halves;
+//   kSrcHalf:    targets 0..n-1 against the sources list[0..n_list),
+//                their cotangents given by list rank;
+//   kTargetHalf: targets list[0..n_list) (cotangents by rank) against
+//                sources 0..n-1; outputs by rank, without the mass term.
+// Every mode skips the self pair.
+enum VjpMode { kAll = 0, kSrcHalf = 1, kTargetHalf = 2 };
+
+template <int ORDER, int BLOCK, int MODE = kAll>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_eval_vjp(
-    SrcPtrs src, CotPtrs cot, int n, double eps2, int slice_len, OutPtrs out,
-    int64_t slice_stride, unsigned acc_mask) {
+    SrcPtrs src, CotPtrs cot, int n, const int32_t *__restrict__ list, int n_list, double eps2,
+    int slice_len, OutPtrs out, int64_t slice_stride, unsigned acc_mask) {
     using T = VTraits<ORDER>;
     constexpr int NG = T::NG, NOUT = T::NOUT, NF = T::NF;
     constexpr int NFP = (NF + 1) & ~1;  // record padded to whole double2
+    constexpr bool MASS = MODE != kTargetHalf;
+    constexpr bool SKIP = MODE != kAll;  // the list modes identify the self pair by particle
     __shared__ double2 tile[BLOCK * NFP / 2];
     const int tid = threadIdx.x;
     const int k = (int)blockIdx.x * BLOCK + tid;
-    const int kc = k < n ? k : n - 1;
+    const int n_tgt = MODE == kTargetHalf ? n_list : n;
+    const int n_src = MODE == kSrcHalf ? n_list : n;
+    const int kr = k < n_tgt ? k : n_tgt - 1;                  // target rank
+    const int kc = MODE == kTargetHalf ? list[kr] : kr;        // target particle
 
     double xk[3], vk[3], ak[3] = {0, 0, 0}, jk[3] = {0, 0, 0}, gk[NG];
 #pragma unroll
@@ -212,37 +232,41 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
     }
     const double mk = src.m[kc];
 #pragma unroll
-    for (int q = 0; q < NG; ++q) gk[q] = cot.g[q][kc];
+    for (int q = 0; q < NG; ++q) gk[q] = MODE == kSrcHalf ? 0.0 : cot.g[q][kr];
 
     double acc[NOUT], hi[NOUT], lo[NOUT];
 #pragma unroll
     for (int q = 0; q < NOUT; ++q) acc[q] = hi[q] = lo[q] = 0.0;
 
     const int jb0 = (int)blockIdx.y * slice_len;
-    const int je = min(n, jb0 + slice_len);
+    const int je = min(n_src, jb0 + slice_len);
+    __shared__ int tile_id[BLOCK];  // source particle of each record (self test)
     for (int jt = jb0; jt < je; jt += BLOCK) {
         __syncthreads();
         {
             double f[NFP];
-            const int jj = jt + tid;
+            const int jj = jt + tid;  // source rank
             if (jj < je) {
+                const int pj = MODE == kSrcHalf ? list[jj] : jj;
+                if constexpr (SKIP) tile_id[tid] = pj;
                 int o = 0;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) f[o++] = src.x[c][jj];
+                for (int c = 0; c < 3; ++c) f[o++] = src.x[c][pj];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) f[o++] = src.v[c][jj];
+                for (int c = 0; c < 3; ++c) f[o++] = src.v[c][pj];
                 if constexpr (ORDER >= 2) {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) f[o++] = src.a[c][jj];
+                    for (int c = 0; c < 3; ++c) f[o++] = src.a[c][pj];
                 }
                 if constexpr (ORDER == 3) {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) f[o++] = src.j[c][jj];
+                    for (int c = 0; c < 3; ++c) f[o++] = src.j[c][pj];
                 }
-                f[o++] = src.m[jj];
+                f[o++] = src.m[pj];
 #pragma unroll
-                for (int q = 0; q < NG; ++q) f[o++] = cot.g[q][jj];
+                for (int q = 0; q < NG; ++q) f[o++] = MODE == kTargetHalf ? 0.0 : cot.g[q][jj];
             } else {
+                if constexpr (SKIP) tile_id[tid] = -1;
 #pragma unroll
                 for (int q = 0; q < NFP; ++q) f[q] = 0.0;
                 f[0] = f[1] = f[2] = kPadPosVjp;  // far and massless, zero cotangent
@@ -274,17 +298,30 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
 #pragma unroll
                 for (int c = 0; c < 3; ++c) jr[c] = f[o++] - jk[c];
             }
-            const double mj = f[o++];
+            // The self pair is left out explicitly: m_k g_k - m_k g_k is not
+            // exactly zero once the first product is fused (fma keeps its
+            // rounding error), and dQ/dr at r = 0 is of order eps^-3. With
+            // both masses set to zero gh is exactly zero; r, v, a, jr are zero
+            // there, so Q and the mass term are too (R^2 set to 1 keeps them
+            // finite when eps = 0).
+            const bool self = MODE == kAll ? (jt + q) == k : tile_id[q] == kc;
+            const double mj = self ? 0.0 : f[o];
+            const double mkp = self ? 0.0 : mk;
+            ++o;
             const double *gj = &f[o];
             double gh[NG];
 #pragma unroll
-            for (int p = 0; p < NG; ++p) gh[p] = fma(mk, gj[p], -mj * gk[p]);
+            for (int p = 0; p < NG; ++p) {
+                if constexpr (MODE == kAll) gh[p] = fma(mkp, gj[p], -mj * gk[p]);
+                else if constexpr (MODE == kSrcHalf) gh[p] = mkp * gj[p];
+                else gh[p] = -mj * gk[p];
+            }
             double r2 = fma(r[2], r[2], fma(r[1], r[1], fma(r[0], r[0], eps2)));
-            if (SKIPSELF && (jt + q) == k) r2 = 1.0;  // r, v, a, jr and gh are all zero here
+            r2 = self ? 1.0 : r2;
             double *xb = acc, *vb = acc + 3;
             double *ab = ORDER >= 2 ? acc + 6 : acc;    // unused for order 1
             double *jb = ORDER == 3 ? acc + 9 : acc;    // unused below order 3
-            pair_vjp<ORDER>(r, v, a, jr, r2, gh, gj, xb, vb, ab, jb, acc[NOUT - 1]);
+            pair_vjp<ORDER, MASS>(r, v, a, jr, r2, gh, gj, xb, vb, ab, jb, acc[NOUT - 1]);
         }
 #pragma unroll
         for (int q = 0; q < NOUT; ++q) {
@@ -292,10 +329,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
             acc[q] = 0.0;
         }
     }
-    if (k < n) {
+    if (k < n_tgt) {
         const int64_t soff = (int64_t)blockIdx.y * slice_stride;
 #pragma unroll
-        for (int q = 0; q < NOUT; ++q) {
+        for (int q = 0; q < (MASS ? NOUT : NOUT - 1); ++q) {
             double *dst = &out.p[q][soff + k];
             const double val = hi[q] + lo[q];
             *dst = ((acc_mask >> q) & 1u) ? *dst + val : val;
@@ -364,38 +401,156 @@ __global__ __launch_bounds__(256) void k_predict_dt_vjp(h6_state cot, int n, h6_
 
 int ceil_div_i(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
-template <int ORDER>
-hipError_t launch_vjp_order(h6_ctx ctx, const SrcPtrs &src, const CotPtrs &cot, int n,
-                            const OutPtrs &out, unsigned acc_mask) {
+// Sum of slice partials [slice][comp][rank] (ld = n_list) added to
+// out.p[comp][list[rank]]: the target half's results scattered to the
+// particles (list entries are distinct, so no two ranks meet).
+__global__ __launch_bounds__(256) void k_reduce_scatter(const double *__restrict__ partial,
+                                                        int64_t ld, int n_split, int ncomp,
+                                                        const int32_t *__restrict__ list,
+                                                        int n_list, OutPtrs out) {
+    const int64_t total = (int64_t)ncomp * n_list;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(idx / n_list);
+        const int k = (int)(idx - (int64_t)c * n_list);
+        double hi = 0.0, lo = 0.0;
+        for (int sl = 0; sl < n_split; ++sl)
+            two_sum_into(hi, lo, partial[((int64_t)sl * ncomp + c) * ld + k]);
+        out.p[c][list[k]] += hi + lo;
+    }
+}
+
+template <int ORDER, int MODE>
+hipError_t launch_vjp_mode(h6_ctx ctx, const SrcPtrs &src, const CotPtrs &cot, int n,
+                           const int32_t *list, int n_list, const OutPtrs &out,
+                           unsigned acc_mask) {
     constexpr int BLOCK = 128;
     constexpr int NOUT = VTraits<ORDER>::NOUT;
-    const int blocks_i = ceil_div_i(n, BLOCK);
-    int split = balanced_split(ctx, 2, BLOCK, n, blocks_i);
-    const int64_t cap = ctx->partial_cap / ((int64_t)NOUT * n);
+    constexpr int NW = MODE == kTargetHalf ? NOUT - 1 : NOUT;  // outputs written
+    const int n_tgt = MODE == kTargetHalf ? n_list : n;
+    const int n_src = MODE == kSrcHalf ? n_list : n;
+    if (n_tgt <= 0 || n_src <= 0) return hipSuccess;
+    const int blocks_i = ceil_div_i(n_tgt, BLOCK);
+    int split = balanced_split(ctx, 2, BLOCK, n_src, blocks_i);
+    const int64_t cap = ctx->partial_cap / ((int64_t)NW * n_tgt);
     if (split > cap) split = (int)std::max<int64_t>(1, cap);
-    int slice_len = ceil_div_i(ceil_div_i(n, split), BLOCK) * BLOCK;
-    split = ceil_div_i(n, slice_len);
+    int slice_len = ceil_div_i(ceil_div_i(n_src, split), BLOCK) * BLOCK;
+    split = ceil_div_i(n_src, slice_len);
+    // the target half always goes through the partials (scattered after)
+    const bool direct = split == 1 && MODE != kTargetHalf;
     OutPtrs dst;
     int64_t slice_stride = 0;
     unsigned mask = acc_mask;
-    if (split == 1) {
+    if (direct) {
         dst = out;
     } else {
         for (int c = 0; c < kMaxOut; ++c) dst.p[c] = nullptr;
-        for (int c = 0; c < NOUT; ++c) dst.p[c] = ctx->partial + (int64_t)c * n;
-        slice_stride = (int64_t)NOUT * n;
+        for (int c = 0; c < NW; ++c) dst.p[c] = ctx->partial + (int64_t)c * n_tgt;
+        slice_stride = (int64_t)NW * n_tgt;
         mask = 0u;  // partials are overwritten; the reduction applies acc_mask
     }
     dim3 grid(blocks_i, split);
-    if (ctx->eps2 == 0.0)
-        hipLaunchKernelGGL((k_eval_vjp<ORDER, BLOCK, true>), grid, dim3(BLOCK), 0, ctx->stream, src,
-                           cot, n, ctx->eps2, slice_len, dst, slice_stride, mask);
-    else
-        hipLaunchKernelGGL((k_eval_vjp<ORDER, BLOCK, false>), grid, dim3(BLOCK), 0, ctx->stream,
-                           src, cot, n, ctx->eps2, slice_len, dst, slice_stride, mask);
+    hipLaunchKernelGGL((k_eval_vjp<ORDER, BLOCK, MODE>), grid, dim3(BLOCK), 0, ctx->stream, src,
+                       cot, n, list, n_list, ctx->eps2, slice_len, dst, slice_stride, mask);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || split == 1) return e;
-    return launch_reduce(ctx, split, NOUT, 0, n, out, acc_mask);
+    if (e != hipSuccess || direct) return e;
+    if constexpr (MODE == kTargetHalf) {
+        int rb = ceil_div_i((int64_t)NW * n_tgt, 256);
+        if (rb > 4096) rb = 4096;
+        hipLaunchKernelGGL(k_reduce_scatter, dim3(rb), dim3(256), 0, ctx->stream, ctx->partial,
+                           (int64_t)n_tgt, split, NW, list, n_tgt, out);
+        return hipGetLastError();
+    } else {
+        return launch_reduce(ctx, split, NOUT, 0, n_tgt, out, acc_mask);
+    }
+}
+
+template <int ORDER>
+hipError_t launch_vjp_order(h6_ctx ctx, const SrcPtrs &src, const CotPtrs &cot, int n,
+                            const OutPtrs &out, unsigned acc_mask) {
+    return launch_vjp_mode<ORDER, kAll>(ctx, src, cot, n, nullptr, 0, out, acc_mask);
+}
+
+// Transpose of the block-step corrector for the active particles, each over
+// its own step (dt_old, ticks): the shared-step transpose with h per
+// particle; cf by rank.
+__global__ __launch_bounds__(256) void k_correct_block_vjp(h6_state cot,
+                                                           const int32_t *__restrict__ active,
+                                                           int n_act,
+                                                           const int64_t *__restrict__ dt_old,
+                                                           h6_force cf) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_act) return;
+    const int i = active[k];
+    const double h = (double)dt_old[i] * (1.0 / (double)((int64_t)1 << kTickBits));
+    const double h2 = h * h, h3 = h2 * h;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double X = cot.x[c][i], V = cot.v[c][i], Ab = cot.a[c][i];
+        const double Jb = cot.j[c][i], Sb = cot.s[c][i], Cb = cot.c[c][i];
+        const double V1 = fma(0.5 * h, X, V);
+        cot.x[c][i] = X;
+        cot.v[c][i] = fma(0.5 * h, X, V1);
+        cot.a[c][i] = fma(0.1 * h2, X, fma(0.5 * h, V1, -60.0 / h3 * Cb));
+        cot.j[c][i] = fma(h3 / 120.0, X, fma(0.1 * h2, V1, -24.0 / h2 * Cb));
+        cot.s[c][i] = fma(h3 / 120.0, V1, -3.0 / h * Cb);
+        cot.c[c][i] = 0.0;
+        cf.a[c][k] = Ab + fma(-0.1 * h2, X, fma(0.5 * h, V1, 60.0 / h3 * Cb));
+        cf.j[c][k] = Jb + fma(h3 / 120.0, X, fma(-0.1 * h2, V1, -36.0 / h2 * Cb));
+        cf.s[c][k] = Sb + fma(h3 / 120.0, V1, 9.0 / h * Cb);
+    }
+}
+
+// Transpose of the block-step predictor: the shared-step transpose with the
+// interval of each particle, d = (t_tick - t_old[i]) ticks.
+__global__ __launch_bounds__(256) void k_predict_block_vjp(h6_state cot, int n,
+                                                           const int64_t *__restrict__ t_old,
+                                                           int64_t t_tick, h6_pred cp) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double h = (double)(t_tick - t_old[i]) * (1.0 / (double)((int64_t)1 << kTickBits));
+    const double h2 = h * h, h3 = h2 * h, h4 = h3 * h, h5 = h4 * h;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double X = cp.x[c][i], V = cp.v[c][i], A = cp.a[c][i];
+        cot.x[c][i] += X;
+        cot.v[c][i] += fma(h, X, V);
+        cot.a[c][i] += fma(0.5 * h2, X, fma(h, V, A));
+        cot.j[c][i] += fma(h3 / 6.0, X, fma(0.5 * h2, V, h * A));
+        cot.s[c][i] += fma(h4 / 24.0, X, fma(h3 / 6.0, V, 0.5 * h2 * A));
+        cot.c[c][i] += fma(h5 / 120.0, X, fma(h4 / 24.0, V, h3 / 6.0 * A));
+    }
+}
+
+// Potential of each particle, phi_i = -sum_{j != i} m_j / sqrt(r^2 + eps^2):
+// one target per lane over LDS tiles of (x, m), compensated per tile.
+constexpr int kPotBlock = 256;
+__global__ __launch_bounds__(kPotBlock) void k_potential(h6_state st, int n, double eps2,
+                                                         double *__restrict__ phi) {
+    __shared__ double4 tile[kPotBlock];
+    const int tid = threadIdx.x;
+    const int i = (int)blockIdx.x * kPotBlock + tid;
+    const int ic = i < n ? i : n - 1;
+    const double xi = st.x[0][ic], yi = st.x[1][ic], zi = st.x[2][ic];
+    double hi = 0.0, lo = 0.0;
+    for (int jt = 0; jt < n; jt += kPotBlock) {
+        __syncthreads();
+        const int jj = jt + tid;
+        tile[tid] = jj < n ? make_double4(st.x[0][jj], st.x[1][jj], st.x[2][jj], st.m[jj])
+                           : make_double4(kPadPosVjp, kPadPosVjp, kPadPosVjp, 0.0);
+        __syncthreads();
+        double acc = 0.0;
+        const int cnt = min(kPotBlock, n - jt);
+        for (int q = 0; q < cnt; ++q) {
+            const double4 t = tile[q];
+            const double dx = t.x - xi, dy = t.y - yi, dz = t.z - zi;
+            const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
+            const bool self = jt + q == ic;
+            acc = fma(self ? 0.0 : t.w, rsqrt_f64(self ? 1.0 : r2), acc);
+        }
+        two_sum_into(hi, lo, acc);
+    }
+    if (i < n) phi[i] = -(hi + lo);
 }
 
 }  // namespace
@@ -420,6 +575,38 @@ hipError_t launch_correct_shared_vjp(h6_ctx ctx, h6_state *cot, int n, const h6_
 hipError_t launch_predict_dt_vjp(h6_ctx ctx, h6_state *cot, int n, const h6_pred *cp, double dt) {
     hipLaunchKernelGGL(k_predict_dt_vjp, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, *cot, n,
                        *cp, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_vjp_active(h6_ctx ctx, const SrcPtrs &src, const double *const *cot, int n,
+                                  const int32_t *active, int n_act, const OutPtrs &out) {
+    CotPtrs cp;
+    for (int q = 0; q < 9; ++q) cp.g[q] = cot[q];
+    // source half with the mass term, added to all ten outputs
+    hipError_t e = launch_vjp_mode<2, kSrcHalf>(ctx, src, cp, n, active, n_act, out, 0x3ffu);
+    if (e != hipSuccess) return e;
+    // target half, scattered (added) to the active particles
+    return launch_vjp_mode<2, kTargetHalf>(ctx, src, cp, n, active, n_act, out, 0x3ffu);
+}
+
+hipError_t launch_correct_block_vjp(h6_ctx ctx, h6_state *cot, const int32_t *active, int n_act,
+                                    const int64_t *dt_old, const h6_force *cf) {
+    if (n_act <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_correct_block_vjp, dim3((n_act + 255) / 256), dim3(256), 0, ctx->stream,
+                       *cot, active, n_act, dt_old, *cf);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict_block_vjp(h6_ctx ctx, h6_state *cot, int n, const int64_t *t_old,
+                                    int64_t t_tick, const h6_pred *cp) {
+    hipLaunchKernelGGL(k_predict_block_vjp, dim3((n + 255) / 256), dim3(256), 0, ctx->stream,
+                       *cot, n, t_old, t_tick, *cp);
+    return hipGetLastError();
+}
+
+hipError_t launch_potential(h6_ctx ctx, const h6_state *st, int n, double *phi) {
+    hipLaunchKernelGGL(k_potential, dim3((n + kPotBlock - 1) / kPotBlock), dim3(kPotBlock), 0,
+                       ctx->stream, *st, n, ctx->eps2, phi);
     return hipGetLastError();
 }
 

@@ -662,6 +662,66 @@ int h6_predict_dt_vjp(h6_ctx ctx, h6_state *cot, int64_t n, const h6_pred *cot_p
     return H6_OK;
 }
 
+int h6_evaluate_vjp_active(h6_ctx ctx, const h6_pred *src, const double *m, int64_t n,
+                           const int32_t *active, int64_t n_act, const h6_force *cot,
+                           const h6_pred *grad_src, double *grad_m) {
+    if (!ctx) return H6_EINVAL;
+    if (!pred_ok(src) || !m || !pred_ok(grad_src) || !grad_m) return fail_arg(ctx, "null array");
+    if (int rc = check_n(ctx, n)) return rc;
+    if (n_act < 0 || n_act > n) return fail_arg(ctx, "n_act out of range");
+    if (n_act == 0) return H6_OK;
+    if (!active || !force_ok(cot)) return fail_arg(ctx, "null array");
+    const double *g[9];
+    for (int c = 0; c < 3; ++c) {
+        g[c] = cot->a[c];
+        g[3 + c] = cot->j[c];
+        g[6 + c] = cot->s[c];
+    }
+    OutPtrs o;
+    for (int c = 0; c < kMaxOut; ++c) o.p[c] = nullptr;
+    for (int c = 0; c < 3; ++c) {
+        o.p[c] = grad_src->x[c];
+        o.p[3 + c] = grad_src->v[c];
+        o.p[6 + c] = grad_src->a[c];
+    }
+    o.p[9] = grad_m;
+    H6_TRY(ctx, launch_eval_vjp_active(ctx, src_from_pred(src, m), g, (int)n, active, (int)n_act, o),
+           "evaluate vjp (active set)");
+    return H6_OK;
+}
+
+int h6_correct_vjp(h6_ctx ctx, h6_state *cot, int64_t n, const int32_t *active, int64_t n_act,
+                   const int64_t *dt_old, const h6_force *cot_force) {
+    if (!ctx) return H6_EINVAL;
+    if (!state_ok(cot, false) || !dt_old) return fail_arg(ctx, "null array");
+    if (int rc = check_n(ctx, n)) return rc;
+    if (n_act < 0 || n_act > n) return fail_arg(ctx, "n_act out of range");
+    if (n_act == 0) return H6_OK;
+    if (!active || !force_ok(cot_force)) return fail_arg(ctx, "null array");
+    H6_TRY(ctx, launch_correct_block_vjp(ctx, cot, active, (int)n_act, dt_old, cot_force),
+           "correct vjp (block)");
+    return H6_OK;
+}
+
+int h6_predict_vjp(h6_ctx ctx, h6_state *cot, int64_t n, const int64_t *t_old, int64_t t_tick,
+                   const h6_pred *cot_pred) {
+    if (!ctx) return H6_EINVAL;
+    if (!state_ok(cot, false) || !t_old || !pred_ok(cot_pred)) return fail_arg(ctx, "null array");
+    if (int rc = check_n(ctx, n)) return rc;
+    H6_TRY(ctx, launch_predict_block_vjp(ctx, cot, (int)n, t_old, t_tick, cot_pred),
+           "predict vjp (block)");
+    return H6_OK;
+}
+
+int h6_potential(h6_ctx ctx, const h6_state *st, int64_t n, double *phi) {
+    if (!ctx) return H6_EINVAL;
+    if (!st || !st->m || !st->x[0] || !st->x[1] || !st->x[2] || !phi)
+        return fail_arg(ctx, "null array");
+    if (int rc = check_n(ctx, n)) return rc;
+    H6_TRY(ctx, launch_potential(ctx, st, (int)n, phi), "potential");
+    return H6_OK;
+}
+
 int h6_init_forces_vjp(h6_ctx ctx, const h6_state *st, int64_t n, h6_state *cot) {
     if (!ctx) return H6_EINVAL;
     if (!state_ok(st, false) || !state_ok(cot, false)) return fail_arg(ctx, "null array");

@@ -181,6 +181,16 @@ hipError_t launch_eval_vjp(h6_ctx ctx, int order, const SrcPtrs &src, const doub
 hipError_t launch_correct_shared_vjp(h6_ctx ctx, h6_state *cot, int n, const h6_force *cf,
                                      double dt);
 hipError_t launch_predict_dt_vjp(h6_ctx ctx, h6_state *cot, int n, const h6_pred *cp, double dt);
+// Block-step adjoint: evaluation VJP over an active set (cot by rank, out
+// dense: xbar, vbar, abar, mbar added), corrector and predictor transposes
+// with per-particle steps and intervals; per-particle potential.
+hipError_t launch_eval_vjp_active(h6_ctx ctx, const SrcPtrs &src, const double *const *cot, int n,
+                                  const int32_t *active, int n_act, const OutPtrs &out);
+hipError_t launch_correct_block_vjp(h6_ctx ctx, h6_state *cot, const int32_t *active, int n_act,
+                                    const int64_t *dt_old, const h6_force *cf);
+hipError_t launch_predict_block_vjp(h6_ctx ctx, h6_state *cot, int n, const int64_t *t_old,
+                                    int64_t t_tick, const h6_pred *cp);
+hipError_t launch_potential(h6_ctx ctx, const h6_state *st, int n, double *phi);
 
 int sched_blocks_for(int64_t n);
 // Measurement hook helpers (api.hip). prof_begin / prof_end bracket a

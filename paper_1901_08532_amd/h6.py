@@ -106,6 +106,14 @@ _SIGS = {
                                     C.POINTER(h6_pred), C.c_double]),
     "h6_init_forces_vjp": (C.c_int, [C.c_void_p, C.POINTER(h6_state), C.c_int64,
                                      C.POINTER(h6_state)]),
+    "h6_evaluate_vjp_active": (C.c_int, [C.c_void_p, C.POINTER(h6_pred), C.c_void_p, C.c_int64,
+                                         C.c_void_p, C.c_int64, C.POINTER(h6_force),
+                                         C.POINTER(h6_pred), C.c_void_p]),
+    "h6_correct_vjp": (C.c_int, [C.c_void_p, C.POINTER(h6_state), C.c_int64, C.c_void_p,
+                                 C.c_int64, C.c_void_p, C.POINTER(h6_force)]),
+    "h6_predict_vjp": (C.c_int, [C.c_void_p, C.POINTER(h6_state), C.c_int64, C.c_void_p,
+                                 C.c_int64, C.POINTER(h6_pred)]),
+    "h6_potential": (C.c_int, [C.c_void_p, C.POINTER(h6_state), C.c_int64, C.c_void_p]),
     "h6_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "h6_profile_read": (C.c_int, [C.c_void_p, C.POINTER(h6_eval_timing), C.c_int,
                                   C.POINTER(C.c_int)]),
@@ -315,6 +323,32 @@ class Context:
         cs, cp = make_state(CS, gm, None), make_pred(CP)
         return self._check(lib().h6_predict_dt_vjp(self._h, C.byref(cs), CS.shape[1], C.byref(cp),
                                                    float(dt)), "h6_predict_dt_vjp")
+
+    def h6_evaluate_vjp_active(self, P, m, active, n_act, CF, GP, gm):
+        """Adds to GP (9, n) and gm (n) the VJP of the evaluation of the
+        active set; CF holds the cotangents by rank, (9, >= n_act)."""
+        _check_dev(P, torch.float64, "h6_evaluate_vjp_active")
+        pr, cf, gp = make_pred(P), make_force(CF), make_pred(GP)
+        return self._check(lib().h6_evaluate_vjp_active(self._h, C.byref(pr), _ptr(m), P.shape[1],
+                                                        _ptr(active), int(n_act), C.byref(cf),
+                                                        C.byref(gp), _ptr(gm)),
+                           "h6_evaluate_vjp_active")
+
+    def h6_correct_vjp(self, CS, gm, active, n_act, dt_old, CF):
+        cs, cf = make_state(CS, gm, None), make_force(CF)
+        return self._check(lib().h6_correct_vjp(self._h, C.byref(cs), CS.shape[1], _ptr(active),
+                                                int(n_act), _ptr(dt_old), C.byref(cf)),
+                           "h6_correct_vjp")
+
+    def h6_predict_vjp(self, CS, gm, t_old, t_tick, CP):
+        cs, cp = make_state(CS, gm, None), make_pred(CP)
+        return self._check(lib().h6_predict_vjp(self._h, C.byref(cs), CS.shape[1], _ptr(t_old),
+                                                int(t_tick), C.byref(cp)), "h6_predict_vjp")
+
+    def h6_potential(self, S, m, phi):
+        st = make_state(S, m, None)
+        return self._check(lib().h6_potential(self._h, C.byref(st), S.shape[1], _ptr(phi)),
+                           "h6_potential")
 
     def h6_init_forces_vjp(self, S, m, CS, gm):
         st, cs = make_state(S, m, None), make_state(CS, gm, None)
