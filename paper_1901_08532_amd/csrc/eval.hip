@@ -16,7 +16,7 @@
 //     split across workgroups so that even a few hundred targets fill 256
 //     CUs; the slices are combined by a separate compensated reduction;
 //   * FP64 throughout; reciprocal square root from the hardware estimate
-//     (v_rsq_f64) refined by one third-order Newton step;
+//     (v_rsq_f64) refined by one Newton step;
 //   * per tile the register sums are flushed into a compensated (hi, lo)
 //     pair, so rounding grows with the number of tiles, not sources;
 //   * no floating-point atomics: results are bitwise reproducible for a

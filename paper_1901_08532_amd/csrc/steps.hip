@@ -5,6 +5,8 @@
 // All of these are bandwidth- or latency-bound elementwise passes over
 // structure-of-arrays FP64 data: one particle per lane, coalesced loads
 // and stores, no LDS except for block-level reductions.
+#include <algorithm>
+
 #include "steps_body.h"
 
 namespace h6 {
@@ -207,6 +209,7 @@ __global__ __launch_bounds__(kSchedThreads) void k_sched_compact(const int64_t *
 
 // ---------------------------------------------------------------- energy
 constexpr int kEnergyThreads = 256;
+constexpr int kEnergyMaxSplit = 16;  // source slices per target block
 
 __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
     s = a + b;
@@ -217,10 +220,13 @@ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e
 // Per particle: potential -m_i/2 sum_{j != i} m_j / sqrt(r^2+eps^2)
 // (compensated over source tiles), kinetic m v^2/2, angular momentum
 // m x cross v; workgroup sums as compensated (hi, lo) trees; the last
-// workgroup adds the workgroup sums in order.
+// workgroup adds the workgroup sums in order. The sources are split into
+// gridDim.y slices of slice_len (whole tiles), so that enough workgroups
+// run; the potential is linear in the slices, and the kinetic and angular
+// momentum terms are taken by the first slice only.
 __global__ __launch_bounds__(kEnergyThreads) void k_energy(h6_state st, int n, double eps2,
-                                                           double *partial, unsigned *counter,
-                                                           double *out) {
+                                                           int slice_len, double *partial,
+                                                           unsigned *counter, double *out) {
     __shared__ double4 tile[kEnergyThreads];  // x, y, z, m
     __shared__ double red_hi[5][kEnergyThreads];
     __shared__ double red_lo[5][kEnergyThreads];
@@ -229,13 +235,16 @@ __global__ __launch_bounds__(kEnergyThreads) void k_energy(h6_state st, int n, d
     const int ic = i < n ? i : n - 1;
     const double xi0 = st.x[0][ic], xi1 = st.x[1][ic], xi2 = st.x[2][ic];
     double phi_hi = 0.0, phi_lo = 0.0;
-    for (int jt = 0; jt < n; jt += kEnergyThreads) {
+    const int jb = (int)blockIdx.y * slice_len;
+    const int je = min(n, jb + slice_len);
+    for (int jt = jb; jt < je; jt += kEnergyThreads) {
         __syncthreads();
         const int jj = jt + tid;
-        tile[tid] = jj < n ? make_double4(st.x[0][jj], st.x[1][jj], st.x[2][jj], st.m[jj])
-                           : make_double4(1.0e18, 1.0e18, 1.0e18, 0.0);
+        tile[tid] = jj < je ? make_double4(st.x[0][jj], st.x[1][jj], st.x[2][jj], st.m[jj])
+                            : make_double4(1.0e18, 1.0e18, 1.0e18, 0.0);
         __syncthreads();
         double acc = 0.0;
+#pragma unroll 4
         for (int q = 0; q < kEnergyThreads; ++q) {
             const double4 r = tile[q];
             const double dx = r.x - xi0, dy = r.y - xi1, dz = r.z - xi2;
@@ -253,12 +262,14 @@ __global__ __launch_bounds__(kEnergyThreads) void k_energy(h6_state st, int n, d
     double v[5] = {0, 0, 0, 0, 0};
     if (i < n) {
         const double m = st.m[i];
-        const double vx = st.v[0][i], vy = st.v[1][i], vz = st.v[2][i];
-        v[0] = 0.5 * m * fma(vx, vx, fma(vy, vy, vz * vz));
         v[1] = -0.5 * m * (phi_hi + phi_lo);
-        v[2] = m * (xi1 * vz - xi2 * vy);
-        v[3] = m * (xi2 * vx - xi0 * vz);
-        v[4] = m * (xi0 * vy - xi1 * vx);
+        if (blockIdx.y == 0) {
+            const double vx = st.v[0][i], vy = st.v[1][i], vz = st.v[2][i];
+            v[0] = 0.5 * m * fma(vx, vx, fma(vy, vy, vz * vz));
+            v[2] = m * (xi1 * vz - xi2 * vy);
+            v[3] = m * (xi2 * vx - xi0 * vz);
+            v[4] = m * (xi0 * vy - xi1 * vx);
+        }
     }
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
@@ -278,27 +289,53 @@ __global__ __launch_bounds__(kEnergyThreads) void k_energy(h6_state st, int n, d
         }
         __syncthreads();
     }
+    const int wg = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    const int n_wg = (int)(gridDim.x * gridDim.y);
     if (tid < 5) {
-        partial[2 * (blockIdx.x * 5 + tid)] = red_hi[tid][0];
-        partial[2 * (blockIdx.x * 5 + tid) + 1] = red_lo[tid][0];
+        partial[2 * (wg * 5 + tid)] = red_hi[tid][0];
+        partial[2 * (wg * 5 + tid) + 1] = red_lo[tid][0];
     }
-    if (!last_workgroup(counter, gridDim.x)) return;
-    if (tid < 5) {
-        double hi = 0.0, lo = 0.0;
-        for (int b = 0; b < (int)gridDim.x; ++b) {
+    if (!last_workgroup(counter, n_wg)) return;
+    // the last workgroup: every thread takes every 256th workgroup sum, then
+    // the same fixed tree (deterministic for a launch shape)
+    double hi[5] = {0, 0, 0, 0, 0}, lo[5] = {0, 0, 0, 0, 0};
+    for (int b = tid; b < n_wg; b += kEnergyThreads) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
             double s, e;
-            two_sum(hi, load_agent(&partial[2 * (b * 5 + tid)]), s, e);
-            hi = s;
-            lo += e + load_agent(&partial[2 * (b * 5 + tid) + 1]);
+            two_sum(hi[q], load_agent(&partial[2 * (b * 5 + q)]), s, e);
+            hi[q] = s;
+            lo[q] += e + load_agent(&partial[2 * (b * 5 + q) + 1]);
         }
-        out[tid] = hi + lo;
     }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        red_hi[q][tid] = hi[q];
+        red_lo[q][tid] = lo[q];
+    }
+    __syncthreads();
+    for (int w = kEnergyThreads / 2; w >= 1; w >>= 1) {
+        if (tid < w) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                double s, e;
+                two_sum(red_hi[q][tid], red_hi[q][tid + w], s, e);
+                red_hi[q][tid] = s;
+                red_lo[q][tid] += red_lo[q][tid + w] + e;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid < 5) out[tid] = red_hi[tid][0] + red_lo[tid][0];
 }
 
 }  // namespace
 
 int sched_blocks_for(int64_t n) { return (int)((n + kSchedChunk - 1) / kSchedChunk); }
-int energy_blocks_for(int64_t n) { return (int)((n + kEnergyThreads - 1) / kEnergyThreads); }
+// workgroup partial slots for n particles (target blocks x the most slices)
+int energy_blocks_for(int64_t n) {
+    return (int)((n + kEnergyThreads - 1) / kEnergyThreads) * kEnergyMaxSplit;
+}
 
 hipError_t launch_predict(h6_ctx ctx, const h6_state *st, int n, int64_t t_tick, double dt,
                           bool shared, const h6_pred *out) {
@@ -347,9 +384,15 @@ hipError_t launch_next_block(h6_ctx ctx, const h6_state *st, int n, int32_t *act
 }
 
 hipError_t launch_energy(h6_ctx ctx, const h6_state *st, int n) {
-    const int nb = energy_blocks_for(n);
-    hipLaunchKernelGGL(k_energy, dim3(nb), dim3(kEnergyThreads), 0, ctx->stream, *st, n, ctx->eps2,
-                       ctx->ered + 8, ctx->counters + 2, ctx->ered);
+    const int nb = (n + kEnergyThreads - 1) / kEnergyThreads;
+    const int tiles = nb;  // source tiles
+    // about four workgroups of four waves per compute unit
+    int split = std::max(1, std::min(kEnergyMaxSplit, (4 * ctx->n_cu + nb - 1) / nb));
+    split = std::min(split, tiles);
+    const int slice_len = ((tiles + split - 1) / split) * kEnergyThreads;
+    split = (n + slice_len - 1) / slice_len;
+    hipLaunchKernelGGL(k_energy, dim3(nb, split), dim3(kEnergyThreads), 0, ctx->stream, *st, n,
+                       ctx->eps2, slice_len, ctx->ered + 8, ctx->counters + 2, ctx->ered);
     return hipGetLastError();
 }
 

@@ -135,7 +135,7 @@ def test_system_energy_and_its_gradient():
     xr, vr, mr = (torch.from_numpy(a).clone().requires_grad_(True) for a in (x, v, m))
     er = ar.energy(xr, vr, mr, eps * eps)
     rx, rv, rm = torch.autograd.grad(er, (xr, vr, mr))
-    assert float(e) == pytest.approx(float(er), rel=1e-13)
+    assert float(e.detach()) == pytest.approx(float(er.detach()), rel=1e-13)
     for g, r in ((gx, rx), (gv, rv), (gm, rm)):
         assert _rel(g.cpu().numpy(), r.numpy()) <= 1e-11
 
