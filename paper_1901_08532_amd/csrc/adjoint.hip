@@ -19,6 +19,7 @@
 // one target per lane, source slices combined by the compensated slice
 // reduction; no floating-point atomics.
 #include <algorithm>
+#include <type_traits>
 
 #include "device_math.h"
 #include "h6_internal.h"
@@ -205,6 +206,95 @@ constexpr double kPadPosVjp = 1.0e18;
 // Every mode skips the self pair.
 enum VjpMode { kAll = 0, kSrcHalf = 1, kTargetHalf = 2 };
 
+// Order-2 pair VJP, factored. With gh = m_k g_j - m_j g_k and
+//   G(g)  = gA.r + gJ.w + gS.u
+//         = gA.r + gJ.v - 3 alpha gJ.r + gS.a - 6 alpha gS.v + c18 gS.r,
+//   c18   = 18 alpha^2 - 3 beta,
+//   Ga(g) = -3 gJ.r - 6 gS.v + 30 alpha gS.r    (dG/dalpha, beta's alpha^2
+//                                                included),
+// the pair's contribution Q . gh = R^-3 G(gh) has the gradients
+//   d/dr: R^-3 (gA - 3 alpha gJ + c18 gS) + sa v + sb a + cr r,
+//   d/dv: R^-3 (gJ - 6 alpha gS) + sa r + 2 sb v,
+//   d/da: R^-3 gS + sb r,
+// with sa = R^-5 Ga(gh), sb = -3 R^-5 gS.r, cr = -3 R^-5 G(gh) - 2 alpha sa
+// - 2 beta' sb, beta' = (v.v + r.a)/R^2. G, Ga and gS.r are linear in g, so
+// they come from six dot products with each of g_j and g_k; the explicit
+// terms of the target's own cotangent, -m_j R^-3 (...)(g_k), are
+// accumulated as three scalar sums (sum m_j R^-3, alpha m_j R^-3,
+// c18 m_j R^-3) and applied to g_k once per slice. MODE drops the g_j
+// part (kTargetHalf) or the g_k part (kSrcHalf); the mass term -R^-3 G(g_j)
+// goes with the g_j part.
+__device__ __forceinline__ void g_terms(const double *g, const double *r, const double *v,
+                                        const double *a, double a3, double a6, double c18,
+                                        double a30, double &G, double &Ga, double &dSr) {
+    const double dAr = dot3(g, r), dJr = dot3(g + 3, r), dJv = dot3(g + 3, v);
+    dSr = dot3(g + 6, r);
+    const double dSv = dot3(g + 6, v), dSa = dot3(g + 6, a);
+    G = fma(c18, dSr, fma(-a6, dSv, fma(-a3, dJr, dAr + dJv) + dSa));
+    Ga = fma(a30, dSr, fma(-6.0, dSv, -3.0 * dJr));
+}
+
+template <int MODE>
+__device__ __forceinline__ void pair_vjp2(const double *r, const double *v, const double *a,
+                                          double r2, double mk, double mj, const double *gj,
+                                          const double *gk, double *acc, double *sacc) {
+    constexpr bool GJ = MODE != kTargetHalf, GK = MODE != kSrcHalf;
+    const double rho = rsqrt_f64(r2);
+    const double rho2 = rho * rho;
+    const double q3 = rho * rho2;
+    const double alpha = dot3(r, v) * rho2;
+    const double bp = (fma(v[2], v[2], fma(v[1], v[1], v[0] * v[0])) + dot3(r, a)) * rho2;
+    const double beta = fma(alpha, alpha, bp);
+    const double a3 = 3.0 * alpha;
+    const double a6 = a3 + a3;
+    const double c18 = fma(6.0 * a3, alpha, -3.0 * beta);
+    const double a30 = 10.0 * a3;
+    double G = 0.0, Ga = 0.0, dS = 0.0, Gj = 0.0;
+    if constexpr (GJ) {
+        double Gaj, dSj;
+        g_terms(gj, r, v, a, a3, a6, c18, a30, Gj, Gaj, dSj);
+        G = mk * Gj;
+        Ga = mk * Gaj;
+        dS = mk * dSj;
+    }
+    if constexpr (GK) {
+        double Gk, Gak, dSk;
+        g_terms(gk, r, v, a, a3, a6, c18, a30, Gk, Gak, dSk);
+        G = fma(-mj, Gk, G);
+        Ga = fma(-mj, Gak, Ga);
+        dS = fma(-mj, dSk, dS);
+    }
+    const double qr = q3 * rho2;
+    const double sa = qr * Ga;
+    const double sb = (-3.0 * qr) * dS;
+    const double cr = fma(-3.0 * qr, G, fma(-2.0 * alpha, sa, (-2.0 * bp) * sb));
+    const double sb2 = sb + sb;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        acc[c] = fma(sa, v[c], fma(sb, a[c], fma(cr, r[c], acc[c])));
+        acc[3 + c] = fma(sa, r[c], fma(sb2, v[c], acc[3 + c]));
+        acc[6 + c] = fma(sb, r[c], acc[6 + c]);
+    }
+    if constexpr (GJ) {
+        const double kq = mk * q3;
+        const double kqa = -a3 * kq, kqc = c18 * kq;
+        const double kqa6 = kqa + kqa;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            acc[c] = fma(kq, gj[c], fma(kqa, gj[3 + c], fma(kqc, gj[6 + c], acc[c])));
+            acc[3 + c] = fma(kq, gj[3 + c], fma(kqa6, gj[6 + c], acc[3 + c]));
+            acc[6 + c] = fma(kq, gj[6 + c], acc[6 + c]);
+        }
+        acc[9] = fma(-q3, Gj, acc[9]);
+    }
+    if constexpr (GK) {
+        const double jq = mj * q3;
+        sacc[0] += jq;
+        sacc[1] = fma(jq, alpha, sacc[1]);
+        sacc[2] = fma(jq, c18, sacc[2]);
+    }
+}
+
 template <int ORDER, int BLOCK, int MODE = kAll>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_eval_vjp(
     SrcPtrs src, CotPtrs cot, int n, const int32_t *__restrict__ list, int n_list, double eps2,
@@ -237,6 +327,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
     double acc[NOUT], hi[NOUT], lo[NOUT];
 #pragma unroll
     for (int q = 0; q < NOUT; ++q) acc[q] = hi[q] = lo[q] = 0.0;
+    // order 2: scalar sums for the target's own cotangent (pair_vjp2)
+    constexpr bool SK = ORDER == 2 && MODE != kSrcHalf;
+    double sacc[3] = {0, 0, 0}, shi[3] = {0, 0, 0}, slo[3] = {0, 0, 0};
 
     const int jb0 = (int)blockIdx.y * slice_len;
     const int je = min(n_src, jb0 + slice_len);
@@ -276,57 +369,88 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
             for (int q = 0; q < NFP / 2; ++q) tile[tid * (NFP / 2) + q] = make_double2(f[2 * q], f[2 * q + 1]);
         }
         __syncthreads();
-        for (int q = 0; q < BLOCK; ++q) {
-            double f[NFP];
+        auto tile_pairs = [&](auto test_self) {
+            for (int q = 0; q < BLOCK; ++q) {
+                double f[NFP];
 #pragma unroll
-            for (int p = 0; p < NFP / 2; ++p) {
-                const double2 d = tile[q * (NFP / 2) + p];
-                f[2 * p] = d.x;
-                f[2 * p + 1] = d.y;
+                for (int p = 0; p < NFP / 2; ++p) {
+                    const double2 d = tile[q * (NFP / 2) + p];
+                    f[2 * p] = d.x;
+                    f[2 * p + 1] = d.y;
+                }
+                int o = 0;
+                double r[3], v[3], a[3] = {0, 0, 0}, jr[3] = {0, 0, 0};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) r[c] = f[o++] - xk[c];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[c] = f[o++] - vk[c];
+                if constexpr (ORDER >= 2) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) a[c] = f[o++] - ak[c];
+                }
+                if constexpr (ORDER == 3) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) jr[c] = f[o++] - jk[c];
+                }
+                // The self pair is left out explicitly: m_k g_k - m_k g_k is not
+                // exactly zero once the first product is fused (fma keeps its
+                // rounding error), and dQ/dr at r = 0 is of order eps^-3. With
+                // both masses set to zero gh is exactly zero; r, v, a, jr are zero
+                // there, so Q and the mass term are too (R^2 set to 1 keeps them
+                // finite when eps = 0).
+                const bool self = decltype(test_self)::value &&
+                                  (MODE == kAll ? (jt + q) == k : tile_id[q] == kc);
+                const double mj = self ? 0.0 : f[o];
+                const double mkp = self ? 0.0 : mk;
+                ++o;
+                const double *gj = &f[o];
+                double r2 = fma(r[2], r[2], fma(r[1], r[1], fma(r[0], r[0], eps2)));
+                r2 = self ? 1.0 : r2;
+                if constexpr (ORDER == 2) {
+                    pair_vjp2<MODE>(r, v, a, r2, mkp, mj, gj, gk, acc, sacc);
+                } else {
+                    double gh[NG];
+#pragma unroll
+                    for (int p = 0; p < NG; ++p) {
+                        if constexpr (MODE == kAll) gh[p] = fma(mkp, gj[p], -mj * gk[p]);
+                        else if constexpr (MODE == kSrcHalf) gh[p] = mkp * gj[p];
+                        else gh[p] = -mj * gk[p];
+                    }
+                    double *xb = acc, *vb = acc + 3;
+                    double *ab = ORDER >= 2 ? acc + 6 : acc;  // unused for order 1
+                    double *jb = ORDER == 3 ? acc + 9 : acc;  // unused below order 3
+                    pair_vjp<ORDER, MASS>(r, v, a, jr, r2, gh, gj, xb, vb, ab, jb, acc[NOUT - 1]);
+                }
             }
-            int o = 0;
-            double r[3], v[3], a[3] = {0, 0, 0}, jr[3] = {0, 0, 0};
-#pragma unroll
-            for (int c = 0; c < 3; ++c) r[c] = f[o++] - xk[c];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) v[c] = f[o++] - vk[c];
-            if constexpr (ORDER >= 2) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) a[c] = f[o++] - ak[c];
-            }
-            if constexpr (ORDER == 3) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) jr[c] = f[o++] - jk[c];
-            }
-            // The self pair is left out explicitly: m_k g_k - m_k g_k is not
-            // exactly zero once the first product is fused (fma keeps its
-            // rounding error), and dQ/dr at r = 0 is of order eps^-3. With
-            // both masses set to zero gh is exactly zero; r, v, a, jr are zero
-            // there, so Q and the mass term are too (R^2 set to 1 keeps them
-            // finite when eps = 0).
-            const bool self = MODE == kAll ? (jt + q) == k : tile_id[q] == kc;
-            const double mj = self ? 0.0 : f[o];
-            const double mkp = self ? 0.0 : mk;
-            ++o;
-            const double *gj = &f[o];
-            double gh[NG];
-#pragma unroll
-            for (int p = 0; p < NG; ++p) {
-                if constexpr (MODE == kAll) gh[p] = fma(mkp, gj[p], -mj * gk[p]);
-                else if constexpr (MODE == kSrcHalf) gh[p] = mkp * gj[p];
-                else gh[p] = -mj * gk[p];
-            }
-            double r2 = fma(r[2], r[2], fma(r[1], r[1], fma(r[0], r[0], eps2)));
-            r2 = self ? 1.0 : r2;
-            double *xb = acc, *vb = acc + 3;
-            double *ab = ORDER >= 2 ? acc + 6 : acc;    // unused for order 1
-            double *jb = ORDER == 3 ? acc + 9 : acc;    // unused below order 3
-            pair_vjp<ORDER, MASS>(r, v, a, jr, r2, gh, gj, xb, vb, ab, jb, acc[NOUT - 1]);
-        }
+        };
+        // in the all-pairs mode a self pair can only occur in the diagonal
+        // tile (slices are whole tiles aligned with the target blocks)
+        if (MODE != kAll || jt == (int)blockIdx.x * BLOCK)
+            tile_pairs(std::true_type{});
+        else
+            tile_pairs(std::false_type{});
 #pragma unroll
         for (int q = 0; q < NOUT; ++q) {
             two_sum_into(hi[q], lo[q], acc[q]);
             acc[q] = 0.0;
+        }
+        if constexpr (SK) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                two_sum_into(shi[q], slo[q], sacc[q]);
+                sacc[q] = 0.0;
+            }
+        }
+    }
+    if constexpr (SK) {
+        // the target's own cotangent: -S0 gA + 3 S1 gJ - S2 gS into xbar,
+        // -S0 gJ + 6 S1 gS into vbar, -S0 gS into abar
+        const double S0 = shi[0] + slo[0], S1 = shi[1] + slo[1], S2 = shi[2] + slo[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            two_sum_into(hi[c], lo[c], fma(-S0, gk[c], fma(3.0 * S1, gk[3 + c], -S2 * gk[6 + c])));
+            two_sum_into(hi[3 + c], lo[3 + c], fma(-S0, gk[3 + c], 6.0 * S1 * gk[6 + c]));
+            two_sum_into(hi[6 + c], lo[6 + c], -S0 * gk[6 + c]);
         }
     }
     if (k < n_tgt) {
