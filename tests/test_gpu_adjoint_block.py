@@ -144,7 +144,8 @@ def _block_grads(ctx, x, v, m, t_end, loss_fn, **kw):
     xt, vt, mt = (t.requires_grad_(True) for t in _dev(x, v, m))
     xT, vT = hermite_block_run(xt, vt, mt, ctx, t_end, **kw)
     loss = loss_fn(xT, vT, xt, vt, mt)
-    return (float(loss),) + tuple(g.cpu().numpy() for g in torch.autograd.grad(loss, (xt, vt, mt)))
+    grads = torch.autograd.grad(loss, (xt, vt, mt))
+    return (float(loss.detach()),) + tuple(g.cpu().numpy() for g in grads)
 
 
 def _sq_loss(xT, vT, *_):
@@ -260,3 +261,47 @@ def test_energy_loss_matches_the_reference(mode):
     assert float(loss) == pytest.approx(float(lr), rel=1e-12)
     for gg, rr in zip(g, r):
         assert _rel(gg, rr) <= 1e-9
+
+
+def test_edge_cases_of_the_block_adjoint_calls():
+    n = 2
+    x = np.array([[0.0, 0.0, 0.0], [3.0, 4.0, 0.0]])
+    v = np.zeros((2, 3))
+    m = np.array([2.0, 5.0])
+    ctx = h6.Context(n, 0.0)
+    S = torch.zeros((18, n), dtype=torch.float64, device=DEV)
+    S[0:3] = torch.from_numpy(x.T).to(DEV)
+    (mt,) = _dev(m)
+    phi = torch.empty(n, dtype=torch.float64, device=DEV)
+    ctx.h6_potential(S, mt, phi)
+    assert np.allclose(phi.cpu().numpy(), [-1.0, -0.4], rtol=1e-15, atol=0)
+    # empty active set: the VJP and the corrector transpose change nothing
+    P = S[0:9].contiguous()
+    G = torch.zeros((9, n), dtype=torch.float64, device=DEV)
+    gm = torch.zeros(n, dtype=torch.float64, device=DEV)
+    none = torch.zeros(1, dtype=torch.int32, device=DEV)
+    CF = torch.zeros((9, 1), dtype=torch.float64, device=DEV)
+    ctx.h6_evaluate_vjp_active(P, mt, none, 0, CF, G, gm)
+    cot = torch.ones((18, n), dtype=torch.float64, device=DEV)
+    dt = torch.full((n,), 1 << 30, dtype=torch.int64, device=DEV)
+    ctx.h6_correct_vjp(cot, gm, none, 0, dt, CF)
+    torch.cuda.synchronize()
+    assert not G.any() and not gm.any() and bool((cot == 1).all())
+    # bad sizes are refused
+    with pytest.raises(h6.H6Error):
+        ctx.h6_evaluate_vjp_active(P, mt, none, 3, CF, G, gm)
+    with pytest.raises(h6.H6Error):
+        ctx.h6_correct_vjp(cot, gm, none, -1, dt, CF)
+
+
+def test_block_run_with_no_block_before_the_end_time():
+    # t_end before the first block: the result is the initial state, and the
+    # gradient of sum |x|^2 + |v|^2 / 2 is (2 x0, v0, 0)
+    n = 32
+    x, v, m = ics.plummer(n, 18)
+    ctx = h6.Context(n, 1e-3)
+    loss, gx, gv, gm = _block_grads(ctx, x, v, m, 0, _sq_loss)
+    assert loss == pytest.approx(float((x ** 2).sum() + 0.5 * (v ** 2).sum()), rel=1e-14)
+    assert np.allclose(gx, 2 * x, rtol=1e-15, atol=0)
+    assert np.allclose(gv, v, rtol=1e-15, atol=0)
+    assert not np.any(gm)

@@ -142,3 +142,16 @@ def test_conservation_study_single_precision_accumulates():
     assert dl["sp"][-1] > 1e3 * max(dl["fp64"].max(), 1e-16)
     with pytest.raises(ValueError):
         conservation.run(n=64, time_units=0.0625, precision="sp", mode="block")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_single_particle_and_empty_active_set(prec):
+    # one particle: no other source, all sums exactly zero; n_act = 0 is a no-op
+    x, v, a, m = _case(1, 3, 1e-4)
+    ctx = h6.Context(1, 1e-4)
+    for g in gpu_evaluate(ctx, x, v, a, m, precision=prec):
+        assert np.array_equal(g, np.zeros((1, 3)))
+    x, v, a, m = _case(100, 3, 1e-4)
+    ctx = h6.Context(100, 1e-4)
+    got = gpu_evaluate(ctx, x, v, a, m, active=np.zeros(0, dtype=np.int32), precision=prec)
+    assert all(g.shape == (0, 3) for g in got)
