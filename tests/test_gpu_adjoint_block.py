@@ -162,7 +162,7 @@ def test_block_adjoint_on_one_level_equals_the_shared_adjoint():
                                 return_velocities=True)
     ls = _sq_loss(xT, vT)
     gxs, gvs, gms = (g.cpu().numpy() for g in torch.autograd.grad(ls, (xt, vt, mt)))
-    assert lb == pytest.approx(float(ls), rel=1e-13)
+    assert lb == pytest.approx(float(ls.detach()), rel=1e-13)
     for gb, gs in ((gxb, gxs), (gvb, gvs), (gmb, gms)):
         assert _rel(gb, gs) <= 1e-10
 
@@ -192,7 +192,7 @@ def test_block_adjoint_matches_the_reference_along_the_oracle_sequence():
     out = ar.block_run(xr, vr, mr, eps * eps, sched)
     lr = _sq_loss(out[0], out[1])
     rx, rv, rm = torch.autograd.grad(lr, (xr, vr, mr))
-    assert lg == pytest.approx(float(lr), rel=1e-12)
+    assert lg == pytest.approx(float(lr.detach()), rel=1e-12)
     for g, r in ((gx, rx), (gv, rv), (gm, rm)):
         assert _rel(g, r.numpy()) <= 1e-9
 
@@ -258,7 +258,7 @@ def test_energy_loss_matches_the_reference(mode):
         out = ar.block_run(xr, vr, mr, eps * eps, ar.block_schedule(x, v, m, eps * eps, SYNC))
     lr = ar.energy(out[0], out[1], mr, eps * eps) - 0.5 * ar.energy(xr, vr, mr, eps * eps)
     r = [t.numpy() for t in torch.autograd.grad(lr, (xr, vr, mr))]
-    assert float(loss) == pytest.approx(float(lr), rel=1e-12)
+    assert float(loss.detach()) == pytest.approx(float(lr.detach()), rel=1e-12)
     for gg, rr in zip(g, r):
         assert _rel(gg, rr) <= 1e-9
 
