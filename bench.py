@@ -78,16 +78,37 @@ def _traffic_per_launch(tag):
     counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
-    want = _eval_sources_sha256()
+    fields = _traffic_fields()
+    if fields.get("eval_source_sha256") != _eval_sources_sha256():
+        return None
+    key = "hbm_bytes_per_launch_" + tag
+    return float(fields[key]) if key in fields else None
+
+
+def _traffic_fields():
+    """key = value lines of the committed traffic record."""
     fields = {}
     for line in open(TRAFFIC_FILE):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             fields[k.strip()] = v.strip()
-    if fields.get("eval_source_sha256") != want:
+    return fields
+
+
+def _executed_flops_per_interaction():
+    """Executed FP64 flops per interaction of the block-loop evaluation
+    (FMA 2, ADD/MUL/TRANS 1) from the committed counter summary, or None
+    once the evaluation sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "bl_eval_fp64_valu_counters.md")
+    if not os.path.exists(path) or not os.path.exists(TRAFFIC_FILE):
         return None
-    key = "hbm_bytes_per_launch_" + tag
-    return float(fields[key]) if key in fields else None
+    # the counter summary and the traffic record are taken for the same sources
+    if _traffic_fields().get("eval_source_sha256") != _eval_sources_sha256():
+        return None
+    for line in open(path):
+        if line.startswith("executed FP64 flops per interaction"):
+            return float(line.rsplit("=", 1)[1])
+    return None
 
 
 def _eval_sources_sha256():
@@ -244,6 +265,43 @@ def main():
         "avg_launch_us": 1e3 * dom["kernel_ms"] / max(1, dom["launches"]),
         "flops_per_launch": FLOPS_PER_INTERACTION * dom["interactions"] / max(1, dom["launches"]),
     }
+    xfl = _executed_flops_per_interaction() if prec == h6.H6_FP64 else None
+    if xfl is not None:
+        roofline["executed_flops_per_interaction"] = xfl
+        roofline["executed_tflops"] = achieved * xfl / FLOPS_PER_INTERACTION
+
+    # timings of single passes on the final, synchronised state, HIP events
+    # on the library's stream (torch's current one), mean of 10: (i) the
+    # a/j/s evaluation of all n particles with its slice reduction, (ii) a
+    # whole step of all n particles (predict, evaluate, reduce, correct)
+    reps = 10
+    Pt = sysg.S[0:9].contiguous()
+    Ft = torch.empty((9, n), dtype=torch.float64, device="cuda")
+    St = sysg.S.clone()
+    Pw = torch.empty((9, n), dtype=torch.float64, device="cuda")
+
+    def _events(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return 1e3 * e0.elapsed_time(e1) / reps
+
+    t_eval = _events(lambda: sysg.ctx.h6_evaluate(Pt, sysg.m, None, n, prec, Ft))
+    t_step = _events(lambda: sysg.ctx.h6_shared_steps(St, sysg.m, Pw, Ft, 2.0 ** -12, 1, prec))
+    timings = {
+        "eval_reduce_all_n_us": t_eval,
+        "eval_reduce_all_n_pct_fp64_peak": 100.0 * FLOPS_PER_INTERACTION * float(n) * n
+                                             / (t_eval * 1e-6) / (FP64_PEAK_TFLOPS * 1e12),
+        "step_all_n_us": t_step,
+        "block_step_avg_us": 1e6 * wall / max(1, blocks),
+        "run_s": wall,
+        "repeats": reps,
+    }
+    _log("eval+reduce of all %d: %.1f us; full step %.1f us" % (n, t_eval, t_step))
 
     # accuracy vs the FP64 oracle on sampled targets of the final, synchronised state
     import oracle
@@ -314,6 +372,7 @@ def main():
         "interactions": inter,
         "eval_kernel_share_of_wall": 1e-3 * eval_ms / wall if wall > 0 else None,
         "eval_by_active_set": by_active,
+        "timings": timings,
         "energy_rel_err_max": drift,
         "accuracy": acc,
         "roofline": roofline,

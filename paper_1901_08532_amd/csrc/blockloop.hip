@@ -465,7 +465,12 @@ __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t s
         const int nt = n_act - k0 < per ? n_act - k0 : per;
         const bool valid = tid < nt;
         int id = 0, lev = 0;
-        if (valid) id = rank_to_particle(A, &rt, k0 + tid);  // overlaps the slice loads
+        OldState old{};
+        if (valid) {
+            // the particle and its old state: loads in flight during the slice sums
+            id = rank_to_particle(A, &rt, k0 + tid);
+            old = load_old<false>(A.st, id);
+        }
         if (w * (64 / seg) < nt) {  // waves holding a target of the round
             // seg lanes per target (contiguous slices: coalesced loads), the
             // nine components' loads of four passes issued together, then a
@@ -502,8 +507,8 @@ __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t s
             double x1[3], v1[3], c1[3], f[9];
 #pragma unroll
             for (int c = 0; c < 9; ++c) f[c] = fs[tid * 9 + c];
-            correct_vals<false>(A.st, id, f, f + 3, f + 6, tn, 0.0, A.eta6, A.lev_min,
-                                A.lev_max, A.flags, x1, v1, c1, &lev);
+            correct_from<false>(old, f, f + 3, f + 6, tn, 0.0, A.eta6, A.lev_min, A.lev_max,
+                                A.flags, x1, v1, c1, &lev);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 A.st.x[c][id] = x1[c];

@@ -69,19 +69,40 @@ __device__ __forceinline__ void predict_one(const h6_state &st, int i, double d,
 }
 
 // ---------------------------------------------------------------- corrector
+// State of one particle before its correction.
+struct OldState {
+    double x[3], v[3], a[3], j[3], s[3];
+    int64_t dt;
+};
+
+template <bool SHARED>
+__device__ __forceinline__ OldState load_old(const h6_state &st, int i) {
+    OldState o;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        o.x[c] = st.x[c][i];
+        o.v[c] = st.v[c][i];
+        o.a[c] = st.a[c][i];
+        o.j[c] = st.j[c][i];
+        o.s[c] = st.s[c][i];
+    }
+    o.dt = SHARED ? 0 : st.dt[i];
+    return o;
+}
+
 // 6th-order Hermite corrector, quintic interpolation of crackle, pop and
 // the fifth derivative at the step end, and the power-of-two step rule.
-// Computes, for particle i and the new a1, j1, s1 (fa, fj, fs), the
-// corrected x1, v1 and the interpolated crackle c1; block steps (SHARED
-// false) also the new level (step 2^-level), taking the step from dt[i].
-// Reads the state only.
+// Computes, for a particle with old state o and the new a1, j1, s1 (fa, fj,
+// fs), the corrected x1, v1 and the interpolated crackle c1; block steps
+// (SHARED false) also the new level (step 2^-level), taking the step from
+// o.dt.
 template <bool SHARED>
-__device__ __forceinline__ void correct_vals(const h6_state &st, int i, const double *fa,
+__device__ __forceinline__ void correct_from(const OldState &o, const double *fa,
                                              const double *fj, const double *fs, int64_t t_next,
                                              double dt_sh, double eta6, int lev_min, int lev_max,
                                              int32_t *flags, double *x1o, double *v1o,
                                              double *c1o, int *lev_out) {
-    const int64_t dt_old = SHARED ? 0 : st.dt[i];
+    const int64_t dt_old = o.dt;
     const double h = SHARED ? dt_sh : (double)dt_old * kTick;
     const double h2 = h * h;
     const double hinv = 1.0 / h;
@@ -90,8 +111,8 @@ __device__ __forceinline__ void correct_vals(const h6_state &st, int i, const do
     bool finite = true;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const double x0 = st.x[c][i], v0 = st.v[c][i];
-        const double a0 = st.a[c][i], j0 = st.j[c][i], s0 = st.s[c][i];
+        const double x0 = o.x[c], v0 = o.v[c];
+        const double a0 = o.a[c], j0 = o.j[c], s0 = o.s[c];
         const double a1 = fa[c], j1 = fj[c], s1 = fs[c];
         // v1 = v0 + h/2 (a0 + a1) - h^2/10 (j1 - j0) + h^3/120 (s0 + s1)
         const double v1 =
@@ -134,6 +155,17 @@ __device__ __forceinline__ void correct_vals(const h6_state &st, int i, const do
         lev_new = lev_max;
     }
     *lev_out = lev_new;
+}
+
+// correct_from with the old state read from st.
+template <bool SHARED>
+__device__ __forceinline__ void correct_vals(const h6_state &st, int i, const double *fa,
+                                             const double *fj, const double *fs, int64_t t_next,
+                                             double dt_sh, double eta6, int lev_min, int lev_max,
+                                             int32_t *flags, double *x1o, double *v1o,
+                                             double *c1o, int *lev_out) {
+    correct_from<SHARED>(load_old<SHARED>(st, i), fa, fj, fs, t_next, dt_sh, eta6, lev_min,
+                         lev_max, flags, x1o, v1o, c1o, lev_out);
 }
 
 // correct_vals, stored in place: x, v, c corrected, a, j, s the new
