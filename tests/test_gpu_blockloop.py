@@ -167,3 +167,32 @@ def test_device_loop_single_particle_and_tiny_systems():
         rc, st = s.run_blocks(SYNC, 0.4, 4, 30)
         assert rc == h6.H6_OK and st.blocks > 0
         assert bool((s.T[0] == SYNC).all())
+
+
+@pytest.mark.parametrize("n,precision,imf", [(65536, h6.H6_FP64, False),
+                                              (262144, h6.H6_MIXED, True)])
+def test_device_loop_full_size_sync_block_against_oracle(n, precision, imf):
+    # the workloads the benchmark times (N = 65536 FP64; N = 262144 power-law
+    # masses, mixed), one sync interval on the device loop. The block at the
+    # sync time has every particle active: its evaluation, in the launch
+    # shape of the loop, left a, j, s in the state and the predicted x, v, a
+    # in the work array, so sampled targets can be checked one by one
+    x, v, m = ics.plummer(n, 2 if not imf else 3)
+    if imf:
+        m = ics.salpeter_masses(n, 33)
+    s = h6.System(x, v, m, EPS)
+    s.startup(eta_s=0.1, lev_min=4, lev_max=30)
+    rc, st = s.run_blocks(1 << (h6.TICK_BITS - 4), 0.4, 4, 30, precision)
+    assert rc == h6.H6_OK and st.blocks > 100
+    assert bool((s.T[0] == (1 << (h6.TICK_BITS - 4))).all())
+    P = s.P.cpu().numpy()
+    xp, vp, ap = P[0:3].T.copy(), P[3:6].T.copy(), P[6:9].T.copy()
+    rng = np.random.Generator(np.random.PCG64(77))
+    idx = np.sort(rng.choice(n, 256 if not imf else 1024, replace=False))
+    want = oracle.forces(xp, vp, m, EPS ** 2, a=ap, idx=idx, order=2)[:3]
+    bound = ({"a": 1e-12, "j": 1e-12, "s": 1e-12} if precision == h6.H6_FP64
+             else {"a": 2e-5, "j": 5e-5, "s": 2e-4})
+    for k, name in enumerate("ajs"):
+        got = s.field(name)[idx]
+        err = vec_rel_err(got, want[k])
+        assert err.max() <= bound[name], (name, float(err.max()))
