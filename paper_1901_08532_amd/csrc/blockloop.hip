@@ -169,7 +169,9 @@ __device__ __forceinline__ int cdiv32(int a, int b) { return (a + b - 1) / b; }
 // one-wave workgroup, predicted arrays): as many slices as fit one round of
 // resident workgroups, down to one 64-source tile per slice (measured on
 // gfx950: for a few hundred targets, one-tile slices over the whole grid
-// beat fewer, longer ones by a third). pc_pairs bounds split * n_act.
+// beat fewer, longer ones by a third); with few slices per group, the
+// slice count that fills the last round of workgroups best. pc_pairs
+// bounds split * n_act.
 __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsigned pc_pairs) {
     int split, kind, groups;
     if (n_act <= kSmall2Max) {
@@ -184,6 +186,24 @@ __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsig
         split = eval_grid / groups;
         const int cap = (n + kTileBlock - 1) / kTileBlock;
         split = split < cap ? split : cap;
+        if (split < 1) split = 1;
+        if (split <= 16) {
+            // few slices per group: the last round of workgroups may be
+            // part-empty. Take the slice count in [split, 4 split] with the
+            // least rounds x slice length (ties: fewer slices).
+            int best = split, best_cost = 0x7fffffff;
+            const int hi = 4 * split < cap ? 4 * split : cap;
+            for (int sp = split; sp <= hi; ++sp) {
+                const int sl = cdiv32(cdiv32(n, sp), 64) * 64;
+                const int units = groups * cdiv32(n, sl);
+                const int cost = cdiv32(units, eval_grid) * sl;
+                if (cost < best_cost) {
+                    best_cost = cost;
+                    best = sp;
+                }
+            }
+            split = best;
+        }
     }
     const unsigned pc = pc_pairs / (unsigned)n_act;
     if ((unsigned)split > pc) split = (int)pc;
