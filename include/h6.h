@@ -12,9 +12,12 @@
  *     (h6_energy) computed on the device;
  *   - Sec. 3 item 4 (kernel steps i-iv): the evaluation stages source
  *     particles through on-chip local memory and skips the self term;
- *   - Sec. 3 item 6: precision is selectable (H6_FP64, H6_MIXED);
+ *   - Sec. 3 item 6: the evaluation arithmetic is selectable (H6_FP64,
+ *     H6_MIXED, and the paper's extended H6_EX and single H6_SP);
  *   - Sec. 2: block time stepping (h6_next_block and the power-of-two
- *     step rule in h6_correct).
+ *     step rule in h6_correct; h6_run_blocks runs the whole loop);
+ *   - reverse mode of the shared- and block-step paths (the *_vjp calls)
+ *     and the per-particle potential (h6_potential) for energy losses.
  *
  * Conventions shared by every call:
  *   - Particle data lives in caller-owned DEVICE memory as structure of
