@@ -486,32 +486,38 @@ __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t s
         const bool valid = tid < nt;
         int id = 0, lev = 0;
         OldState old{};
+        const bool reducer = w * (64 / seg) < nt;  // waves holding a target of the round
+        // seg lanes per target (contiguous slices: coalesced loads), the nine
+        // components' loads of four passes issued together, then a fixed
+        // butterfly within the segment
+        const double *__restrict__ part = A.partial;
+        const int r = w * (64 / seg) + lane / seg;  // target of this lane in the round
+        const int o = lane & (seg - 1);
+        const bool has = reducer && r < nt;
+        const int64_t base = (int64_t)(k0 + (has ? r : 0)) * 9 * split;
+        double x[4][9];
+        auto load_slices = [&](int sl0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int sl = sl0 + q * seg + o;
+                const bool in = has && sl < split;
+#pragma unroll
+                for (int c = 0; c < 9; ++c) x[q][c] = in ? part[base + c * split + sl] : 0.0;
+            }
+        };
+        // the first slices, then the particle and its old state (list, then
+        // state: two dependent loads), all in flight together
+        if (reducer) load_slices(0);
         if (valid) {
-            // the particle and its old state: loads in flight during the slice sums
             id = rank_to_particle(A, &rt, k0 + tid);
             old = load_old<false>(A.st, id);
         }
-        if (w * (64 / seg) < nt) {  // waves holding a target of the round
-            // seg lanes per target (contiguous slices: coalesced loads), the
-            // nine components' loads of four passes issued together, then a
-            // fixed butterfly within the segment
-            const double *__restrict__ part = A.partial;
-            const int r = w * (64 / seg) + lane / seg;  // target of this lane in the round
-            const int o = lane & (seg - 1);
-            const bool has = r < nt;
-            const int64_t base = (int64_t)(k0 + (has ? r : 0)) * 9 * split;
+        if (reducer) {
             double s[9], comp[9];
 #pragma unroll
             for (int c = 0; c < 9; ++c) s[c] = comp[c] = 0.0;
             for (int sl0 = 0; sl0 < split; sl0 += 4 * seg) {
-                double x[4][9];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int sl = sl0 + q * seg + o;
-                    const bool in = has && sl < split;
-#pragma unroll
-                    for (int c = 0; c < 9; ++c) x[q][c] = in ? part[base + c * split + sl] : 0.0;
-                }
+                if (sl0 != 0) load_slices(sl0);
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll

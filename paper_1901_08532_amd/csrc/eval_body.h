@@ -281,6 +281,30 @@ __device__ __forceinline__ void eval_small_body(const SRC &S, int n, int n_act, 
                                                 int64_t slice_stride, int wave, int sl) {
     constexpr int PASS = TPW == 1 ? kSmallPass : kSmallPass / 2;  // register budget
     const int lane = threadIdx.x & 63;
+    const int jb = sl * slice_len;
+    const int je = min(n, jb + slice_len);
+    // sources of one pass: their loads do not depend on the targets, so the
+    // first pass is fetched before the targets' (list, then state) loads
+    auto load_pass = [&](int jp, double (*xs)[3], double (*vs)[3], double (*as)[3], double *ms) {
+#pragma unroll
+        for (int u = 0; u < PASS; ++u) {
+            const int j = jp + u * 64 + lane;
+            if (j < je) {
+                double jd[3];
+                S.template get<2>(j, xs[u], vs[u], as[u], jd);
+                ms[u] = S.mass(j);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    xs[u][c] = kPadPos;
+                    vs[u][c] = as[u][c] = 0.0;
+                }
+                ms[u] = 0.0;
+            }
+        }
+    };
+    double xs[PASS][3], vs[PASS][3], as[PASS][3], ms[PASS];
+    load_pass(jb, xs, vs, as, ms);
     double xi[TPW][3], vi[TPW][3], ai[TPW][3];
     int pid[TPW];
 #pragma unroll
@@ -298,27 +322,9 @@ __device__ __forceinline__ void eval_small_body(const SRC &S, int n, int n_act, 
 #pragma unroll
         for (int q = 0; q < 9; ++q) acc[t][q] = hi[t][q] = lo[t][q] = 0.0;
 
-    const int jb = sl * slice_len;
-    const int je = min(n, jb + slice_len);
     int passes = 0;
     for (int jp = jb; jp < je; jp += PASS * 64) {
-        double xs[PASS][3], vs[PASS][3], as[PASS][3], ms[PASS];
-#pragma unroll
-        for (int u = 0; u < PASS; ++u) {
-            const int j = jp + u * 64 + lane;
-            if (j < je) {
-                double jd[3];
-                S.template get<2>(j, xs[u], vs[u], as[u], jd);
-                ms[u] = S.mass(j);
-            } else {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    xs[u][c] = kPadPos;
-                    vs[u][c] = as[u][c] = 0.0;
-                }
-                ms[u] = 0.0;
-            }
-        }
+        if (jp != jb) load_pass(jp, xs, vs, as, ms);
 #pragma unroll
         for (int u = 0; u < PASS; ++u) {
             const int j = jp + u * 64 + lane;
