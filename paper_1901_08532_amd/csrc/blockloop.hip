@@ -523,10 +523,10 @@ __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t s
 #pragma unroll
                     for (int c = 0; c < 9; ++c) neumaier(s[c], comp[c], x[q][c]);
             }
-            seg_comp_sum_n<9>(s, comp, seg);
+            seg_comp_reduce_n<9>(s, comp, seg);  // totals in the segment's last lane
 #pragma unroll
             for (int c = 0; c < 9; ++c)
-                if (has && o == 0) fs[r * 9 + c] = s[c] + comp[c];
+                if (has && o == seg - 1) fs[r * 9 + c] = s[c] + comp[c];
         }
         __syncthreads();
         if (valid) {

@@ -56,11 +56,12 @@ __device__ __forceinline__ void wave_comp_sum(double &s, double &c) {
     }
 }
 
-// A double moved across lanes by a DPP lane pattern (both 32-bit halves).
-template <int CTRL>
+// A double moved across lanes by a DPP lane pattern (both 32-bit halves);
+// lanes of rows outside ROWS get 0.
+template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ double dpp_f64(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 
@@ -105,6 +106,35 @@ __device__ __forceinline__ void seg_comp_sum_n(double *s, double *c, int seg) {
     if (seg >= 16) comp_stage<NV, 0x140>(s, c, (lane & 8) != 0, 8);  // row_mirror
     if (seg >= 32) comp_stage<NV, -1>(s, c, (lane & 16) != 0, 16);
     if (seg >= 64) comp_stage<NV, -1>(s, c, (lane & 32) != 0, 32);
+}
+
+// One row-broadcast stage for NV compensated pairs: the lanes of the rows in
+// ROWS merge the value of the last lane of an earlier row (DPP row_bcast:15
+// takes lane 15 of the row before, row_bcast:31 lane 31) into their own,
+// the earlier rows' value first; the other rows merge zero (no change).
+template <int NV, int CTRL, int ROWS>
+__device__ __forceinline__ void bcast_stage(double *s, double *c) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double a = dpp_f64<CTRL, ROWS>(s[q]), ac = dpp_f64<CTRL, ROWS>(c[q]);
+        comp_merge(a, ac, s[q], c[q]);
+        s[q] = a;
+        c[q] = ac;
+    }
+}
+
+// Sums of NV compensated pairs within aligned segments of seg lanes (seg a
+// power of two up to 64, uniform across the wave), valid in the LAST lane of
+// each segment (deterministic for a given seg). Within 16-lane rows the
+// butterfly of seg_comp_sum_n; across rows, instead of the two exchanges
+// through LDS, two DPP row broadcasts: row_bcast:15 adds row 0 into row 1
+// and row 2 into row 3, then (seg 64) row_bcast:31 adds rows 0-1 into
+// rows 2-3, so that lane 63 holds the wave's total.
+template <int NV>
+__device__ __forceinline__ void seg_comp_reduce_n(double *s, double *c, int seg) {
+    seg_comp_sum_n<NV>(s, c, seg < 16 ? seg : 16);
+    if (seg >= 32) bcast_stage<NV, 0x142, 0xA>(s, c);  // row_bcast:15 into rows 1, 3
+    if (seg >= 64) bcast_stage<NV, 0x143, 0xC>(s, c);  // row_bcast:31 into rows 2, 3
 }
 
 }  // namespace h6

@@ -364,12 +364,12 @@ __device__ __forceinline__ void eval_small_body(const SRC &S, int n, int n_act, 
             sv[t * 9 + q] = hi[t][q];
             cv[t * 9 + q] = lo[t][q];
         }
-    seg_comp_sum_n<TPW * 9>(sv, cv, 64);
+    seg_comp_reduce_n<TPW * 9>(sv, cv, 64);  // totals in lane 63
     const int64_t soff = (int64_t)sl * slice_stride;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
         const int k = wave * TPW + t;
-        if (lane == 0 && k < n_act)
+        if (lane == 63 && k < n_act)
 #pragma unroll
             for (int q = 0; q < 9; ++q)
                 out.p[q][soff + k * out.kstride] = sv[t * 9 + q] + cv[t * 9 + q];

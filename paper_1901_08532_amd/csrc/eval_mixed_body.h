@@ -174,6 +174,34 @@ __device__ __forceinline__ void mixed_small_body(const SRC &S, int n, int n_act,
     static_assert(kChunk % kPassM == 0, "flush on pass boundaries");
     const int lane = threadIdx.x & 63;
     const float eps2f = (float)eps2;
+    const int jb = sl * slice_len;
+    const int je = min(n, jb + slice_len);
+    // sources of one pass: independent of the targets, so the first pass is
+    // fetched before the targets' (list, then state) loads
+    auto load_pass = [&](int jp, double (*xs)[3], double (*vs)[3], float (*as)[3], float *ms) {
+#pragma unroll
+        for (int u = 0; u < kPassM; ++u) {
+            const int j = jp + u * 64 + lane;
+            if (j < je) {
+                double ad[3], jd[3];
+                S.template get<2>(j, xs[u], vs[u], ad, jd);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) as[u][c] = (float)ad[c];
+                ms[u] = (float)S.mass(j);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    xs[u][c] = kPadPosMixed;
+                    vs[u][c] = 0.0;
+                    as[u][c] = 0.0f;
+                }
+                ms[u] = 0.0f;
+            }
+        }
+    };
+    double xs[kPassM][3], vs[kPassM][3];
+    float as[kPassM][3], ms[kPassM];
+    load_pass(jb, xs, vs, as, ms);
     double xi[TPW][3], vi[TPW][3];
     float ai[TPW][3];
     int pid[TPW];
@@ -197,31 +225,9 @@ __device__ __forceinline__ void mixed_small_body(const SRC &S, int n, int n_act,
             acc32[t][q] = 0.0f;
             hi[t][q] = lo[t][q] = 0.0;
         }
-    const int jb = sl * slice_len;
-    const int je = min(n, jb + slice_len);
     int since_flush = 0;
     for (int jp = jb; jp < je; jp += kPassM * 64) {
-        double xs[kPassM][3], vs[kPassM][3];
-        float as[kPassM][3], ms[kPassM];
-#pragma unroll
-        for (int u = 0; u < kPassM; ++u) {
-            const int j = jp + u * 64 + lane;
-            if (j < je) {
-                double ad[3], jd[3];
-                S.template get<2>(j, xs[u], vs[u], ad, jd);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) as[u][c] = (float)ad[c];
-                ms[u] = (float)S.mass(j);
-            } else {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    xs[u][c] = kPadPosMixed;
-                    vs[u][c] = 0.0;
-                    as[u][c] = 0.0f;
-                }
-                ms[u] = 0.0f;
-            }
-        }
+        if (jp != jb) load_pass(jp, xs, vs, as, ms);
 #pragma unroll
         for (int u = 0; u < kPassM; ++u) {
             const int j = jp + u * 64 + lane;
@@ -263,12 +269,12 @@ __device__ __forceinline__ void mixed_small_body(const SRC &S, int n, int n_act,
             sv[t * 9 + q] = hi[t][q];
             cv[t * 9 + q] = lo[t][q];
         }
-    seg_comp_sum_n<TPW * 9>(sv, cv, 64);
+    seg_comp_reduce_n<TPW * 9>(sv, cv, 64);  // totals in lane 63
     const int64_t soff = (int64_t)sl * slice_stride;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
         const int k = wave * TPW + t;
-        if (lane == 0 && k < n_act)
+        if (lane == 63 && k < n_act)
 #pragma unroll
             for (int q = 0; q < 9; ++q)
                 out.p[q][soff + k * out.kstride] = sv[t * 9 + q] + cv[t * 9 + q];
