@@ -96,12 +96,38 @@ struct RankTable {
     int off[kLevels];
 };
 
-__device__ __forceinline__ void load_rank_table(RankTable *rt, const LoopDesc *__restrict__ d) {
-    for (int L = threadIdx.x; L < kLevels; L += blockDim.x) rt->off[L] = d->off[L];
+// The descriptor fields a kernel of the loop reads, loaded together at its
+// start (one round trip to memory instead of one per dependent branch);
+// thread t < kLevels also takes off[t] and cnt[t]. Needs blockDim.x >= kLevels.
+struct DescHead {
+    int64_t t_next;
+    unsigned long long sel;
+    int n_act, split, slice_len, groups, kind, L0, lv_hi;
+    int my_off, my_cnt;
+};
+__device__ __forceinline__ DescHead load_head(const LoopDesc *__restrict__ d) {
+    DescHead h;
+    h.t_next = d->t_next;
+    h.sel = d->sel;
+    h.n_act = d->n_act;
+    h.split = d->split;
+    h.slice_len = d->slice_len;
+    h.groups = d->groups;
+    h.kind = d->kind;
+    h.L0 = d->L0;
+    h.lv_hi = d->lv_hi;
+    const int t = threadIdx.x < kLevels ? threadIdx.x : 0;
+    h.my_off = d->off[t];
+    h.my_cnt = d->cnt[t];
+    return h;
+}
+// The rank table from a loaded head (every thread must call it).
+__device__ __forceinline__ void rank_table_from(RankTable *rt, const DescHead &h) {
+    if (threadIdx.x < kLevels) rt->off[threadIdx.x] = h.my_off;
     if (threadIdx.x == 0) {
-        rt->L0 = d->L0;
-        rt->hi = d->lv_hi;
-        rt->sel = d->sel;
+        rt->L0 = h.L0;
+        rt->hi = h.lv_hi;
+        rt->sel = h.sel;
     }
     __syncthreads();
 }
@@ -350,10 +376,11 @@ template <bool MIXED, bool SKIPSELF>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_bl_eval(
     LoopArgs A, int64_t seq) {
     const LoopDesc *__restrict__ d = A.desc + (seq & 1);
-    const int n_act = d->n_act;
+    const DescHead h = load_head(d);
+    const int n_act = h.n_act;
     if (n_act == 0) return;
-    const int split = d->split, slice_len = d->slice_len, groups = d->groups;
-    const int kind = d->kind;
+    const int split = h.split, slice_len = h.slice_len, groups = h.groups;
+    const int kind = h.kind;
     // slice sums at partial[(k * 9 + c) * split + sl]: a target's slices are
     // contiguous for the finishing reduction
     OutPtrs out;
@@ -364,7 +391,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const int units = groups * split;
     if ((int)blockIdx.x >= units) return;
     __shared__ RankTable rt;
-    load_rank_table(&rt, d);
+    rank_table_from(&rt, h);
     if (kind == 0) {
         const ListPredSrc S{A, &rt};
         for (int u = blockIdx.x; u < units; u += gridDim.x) {
@@ -379,7 +406,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         }
         return;
     }
-    const StateSrc S{A, &rt, d->t_next};
+    const StateSrc S{A, &rt, h.t_next};
     for (int u = blockIdx.x; u < units; u += gridDim.x) {
         const int g = u / split, sl = u - g * split;
         if (kind == 1) {
@@ -454,7 +481,8 @@ __device__ __forceinline__ void neumaier(double &s, double &comp, double x) {
 __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t seq) {
     const LoopDesc *__restrict__ d = A.desc + (seq & 1);
     LoopDesc *dn = A.desc + ((seq + 1) & 1);
-    const int n_act = d->n_act;
+    const DescHead h = load_head(d);
+    const int n_act = h.n_act;
     if (n_act == 0) {
         // nothing due before t_end: carry the final descriptor forward
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -463,23 +491,23 @@ __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t s
         }
         return;
     }
-    const int split = d->split;
+    const int split = h.split;
     const int seg = fin_seg(split);
     const int per = fin_per_round(split);
     const int workers = fin_workers(n_act, split);
     if ((int)blockIdx.x >= workers) return;
-    const int64_t tn = d->t_next;
+    const int64_t tn = h.t_next;
     const bool solo = workers == 1;  // no other workgroup: tallies in LDS, no device atomics
     __shared__ double fs[kFinThreads * 9];
     __shared__ RankTable rt;
     __shared__ int cur_cnt[kLevels];
     __shared__ Tally tally;
-    for (int L = threadIdx.x; L < kLevels; L += blockDim.x) {
-        cur_cnt[L] = d->cnt[L];
-        tally.reb[L] = 0u;
+    if (threadIdx.x < kLevels) {
+        cur_cnt[threadIdx.x] = h.my_cnt;
+        tally.reb[threadIdx.x] = 0u;
     }
     if (threadIdx.x == 0) tally.app = 0u;
-    load_rank_table(&rt, d);  // ends with a barrier
+    rank_table_from(&rt, h);  // ends with a barrier
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int k0 = blockIdx.x * per; k0 < n_act; k0 += workers * per) {
         const int nt = n_act - k0 < per ? n_act - k0 : per;
