@@ -34,7 +34,9 @@
  *     thread-safe; distinct contexts are independent.
  *   - Softening is Plummer: the pair potential is -m / sqrt(r^2 + eps^2).
  *     With eps > 0 the self term is exactly zero; with eps == 0 it is
- *     skipped explicitly (particles must then never coincide).
+ *     skipped explicitly (particles must then never coincide). The
+ *     FP32-based arithmetics skip it too when eps^2 is below the smallest
+ *     normal FP32 number (eps below about 1.1e-19), where it rounds away.
  */
 #ifndef H6_H
 #define H6_H
@@ -114,7 +116,8 @@ typedef struct {
  * Create a context for systems of up to n_max particles with softening
  * length eps (>= 0). hip_stream is a hipStream_t (NULL: the null stream).
  * Allocates the scratch buffers on the current device.
- * Errors: H6_EINVAL (n_max < 1, eps < 0 or not finite, ctx NULL),
+ * Errors: H6_EINVAL (n_max < 1 or above 2^30, eps < 0 or not finite,
+ * ctx NULL),
  * H6_ENOMEM, H6_EHIP.
  */
 int h6_create(h6_ctx *ctx, int64_t n_max, double eps, void *hip_stream);

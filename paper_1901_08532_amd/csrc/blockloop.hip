@@ -708,7 +708,7 @@ hipError_t bl_enqueue_block(h6_ctx ctx, const LoopArgs &A, int precision, int64_
         hipError_t pe = prof_events(ctx, &ev0, &ev1);
         if (pe != hipSuccess) return pe;
     }
-    const bool skip = A.eps2 == 0.0;
+    const bool skip = self_pair_masked(A.eps2, precision);
     const bool mixed = precision == H6_MIXED;
     // with the measurement hook on, the events are those of the dispatch
     // itself (no separate marker packets in the stream)

@@ -283,7 +283,7 @@ hipError_t launch_eval(h6_ctx ctx, int order, int precision, const SrcPtrs &src,
     const int out0 = order == 3 ? 6 : 0;
     const int per_block = cfg.block * cfg.ipl;
     dim3 grid(ceil_div(n_act, per_block), cfg.n_split);
-    const bool skipself = ctx->eps2 == 0.0;
+    const bool skipself = self_pair_masked(ctx->eps2, precision);
 
     OutPtrs dst;
     int64_t slice_stride = 0;

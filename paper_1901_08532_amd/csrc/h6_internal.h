@@ -34,6 +34,16 @@ struct OutPtrs {
     int64_t kstride = 1;
 };
 
+// Whether the evaluation must mask the self pair. With a softening that is
+// nonzero in the arithmetic of the pair terms the self pair has r = v = a = 0
+// and contributes exactly zero; without it, r^2 = 0 and the term is 0 * inf.
+// The FP32-based arithmetics (mixed, EX, SP) see eps^2 rounded to FP32, where
+// a softening below ~1e-19 becomes zero or subnormal.
+inline bool self_pair_masked(double eps2, int precision) {
+    if (precision == H6_FP64) return eps2 == 0.0;
+    return (float)eps2 < 1.17549435e-38f;  // below the smallest normal FP32
+}
+
 // ---- device-resident block loop (blockloop.hip)
 constexpr int kLevels = kTickBits + 1;  // levels 0..40: step 2^-level
 constexpr int kSmall2Max = 48;          // largest active set of the source-parallel kinds

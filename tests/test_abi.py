@@ -44,6 +44,7 @@ def test_null_context_and_bad_create_arguments():
     assert L.h6_create(C.byref(out), 0, 0.1, None) == h6.H6_EINVAL
     assert L.h6_create(C.byref(out), 10, -1.0, None) == h6.H6_EINVAL
     assert L.h6_create(C.byref(out), 10, float("nan"), None) == h6.H6_EINVAL
+    assert L.h6_create(C.byref(out), (1 << 30) + 1, 0.1, None) == h6.H6_EINVAL
     assert out.value is None
     assert L.h6_destroy(None) == h6.H6_OK
     st = h6.h6_state()

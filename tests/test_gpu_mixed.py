@@ -108,3 +108,40 @@ def test_mixed_energy_drift_within_twice_fp64():
             worst = max(worst, abs(sum(s.energy()[:2]) - e0) / abs(e0))
         drift[prec] = worst
     assert drift[h6.H6_MIXED] <= 2.0 * drift[h6.H6_FP64], drift
+
+
+@pytest.mark.parametrize("prec", [h6.H6_MIXED, h6.H6_EX, h6.H6_SP])
+def test_fp32_arithmetics_mask_self_pair_when_softening_rounds_away(prec):
+    # eps = 1e-25: eps^2 = 1e-50 is nonzero in FP64 but zero in FP32, so the
+    # self pair of the FP32-based arithmetics has r^2 = 0 and must be masked
+    # as with eps = 0; the results equal those at eps = 0 to the stated bound
+    n = 1000
+    x, v, _ = ics.plummer(n, 7)
+    m = ics.salpeter_masses(n, 77)
+    a, _, _, _ = oracle.forces(x, v, m, 0.0, order=1)
+    bound = {h6.H6_MIXED: BOUND, h6.H6_EX: {"a": 2e-12, "j": 4e-12, "s": 1e-11},
+             h6.H6_SP: {"a": 1e-4, "j": 2e-4, "s": 5e-4}}[prec]
+    ctx = h6.Context(n, 1e-25)
+    for act in (None, np.array([0, 5, 999], dtype=np.int32)):
+        got = gpu_evaluate(ctx, x, v, a, m, active=act, precision=prec)
+        idx = None if act is None else act.astype(np.int64)
+        want = oracle.forces(x, v, m, 1e-50, a=a, idx=idx, order=2)[:3]
+        for name, g, w in zip("ajs", got, want):
+            assert np.all(np.isfinite(g)), name
+            assert vec_rel_err(g, w).max() <= bound[name], name
+
+
+def test_mixed_block_loop_with_vanishing_softening_stays_finite():
+    # the device-resident loop takes the same decision for its mixed kernels
+    n = 512
+    x, v, m = ics.plummer(n, 12)
+    runs = {}
+    for prec in (h6.H6_FP64, h6.H6_MIXED):
+        s = h6.System(x, v, m, 1e-25)
+        s.startup(eta_s=0.1, lev_min=4, lev_max=30)
+        rc, st = s.run_blocks(1 << (h6.TICK_BITS - 6), 0.4, 4, 30, prec)
+        assert rc == h6.H6_OK
+        runs[prec] = s.field("x")
+        assert np.all(np.isfinite(runs[prec]))
+    d = np.abs(runs[h6.H6_MIXED] - runs[h6.H6_FP64]).max()
+    assert d <= 1e-6, d
