@@ -214,15 +214,18 @@ __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsig
         split = split < cap ? split : cap;
         if (split < 1) split = 1;
         if (split <= 16) {
-            // few slices per group: the last round of workgroups may be
-            // part-empty. Take the slice count in [split, 4 split] with the
-            // least rounds x slice length (ties: fewer slices).
+            // few slices per group: the last round of units may leave SIMDs
+            // idle. The grid holds two waves per SIMD, which share its issue
+            // rate, so a round is one unit per SIMD, not per workgroup. Take
+            // the slice count in [split, 4 split] with the least rounds x
+            // slice length (ties: fewer slices).
+            const int simds = eval_grid / 2;
             int best = split, best_cost = 0x7fffffff;
             const int hi = 4 * split < cap ? 4 * split : cap;
             for (int sp = split; sp <= hi; ++sp) {
                 const int sl = cdiv32(cdiv32(n, sp), 64) * 64;
                 const int units = groups * cdiv32(n, sl);
-                const int cost = cdiv32(units, eval_grid) * sl;
+                const int cost = cdiv32(units, simds) * sl;
                 if (cost < best_cost) {
                     best_cost = cost;
                     best = sp;

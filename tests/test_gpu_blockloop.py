@@ -169,6 +169,49 @@ def test_device_loop_single_particle_and_tiny_systems():
         assert bool((s.T[0] == SYNC).all())
 
 
+@pytest.mark.parametrize("precision", [h6.H6_FP64, h6.H6_MIXED])
+@pytest.mark.parametrize("n_act", [24000, 44000])
+def test_device_loop_tile_units_beyond_the_grid(precision, n_act):
+    # one block of n_act of 65536 particles: the device loop cuts the sources
+    # into more tile units (target group x slice) than it launches workgroups
+    # (3008 and 6880 units for 2048 workgroups), which take them in rounds.
+    # Every unit must be evaluated exactly once: the state matches the host
+    # loop's, and the forces left by the block match the oracle on the
+    # predicted arrays for sampled targets.
+    n = 65536
+    x, v, m = ics.plummer(n, 21)
+    rng = np.random.Generator(np.random.PCG64(n_act))
+    act = np.sort(rng.choice(n, n_act, replace=False))
+    dt = np.full(n, 1 << (TB - 4), dtype=np.int64)
+    dt[act] = 1 << (TB - 5)
+    systems = []
+    for host_loop in (False, True):
+        s = h6.System(x, v, m, EPS)
+        s.startup()
+        s.T[0].zero_()
+        s.T[1].copy_(torch.from_numpy(dt).to(DEV))
+        rc, st = s.run_blocks(1 << (TB - 5), 0.4, 4, 30, precision, host_loop=host_loop)
+        assert rc == h6.H6_OK
+        assert (st.blocks, st.particle_steps) == (1, n_act)
+        systems.append(s)
+    a, b = systems
+    bound = ({"a": 1e-12, "j": 1e-12, "s": 1e-12} if precision == h6.H6_FP64
+             else {"a": 2e-5, "j": 5e-5, "s": 2e-4})
+    if precision == h6.H6_FP64:
+        assert torch.equal(a.T, b.T)
+    for name in ("x", "v"):
+        assert vec_rel_err(a.field(name), b.field(name)).max() < 1e-9, name
+    for name in "ajs":  # two evaluations, each within the bound of the oracle's
+        assert vec_rel_err(a.field(name), b.field(name)).max() < 2 * bound[name], name
+    P = a.P.cpu().numpy()
+    xp, vp, ap = P[0:3].T.copy(), P[3:6].T.copy(), P[6:9].T.copy()
+    idx = np.sort(rng.choice(act, 128, replace=False))
+    want = oracle.forces(xp, vp, m, EPS ** 2, a=ap, idx=idx, order=2)[:3]
+    for k, name in enumerate("ajs"):
+        err = vec_rel_err(a.field(name)[idx], want[k])
+        assert err.max() <= bound[name], (name, float(err.max()))
+
+
 @pytest.mark.parametrize("n,precision,imf", [(65536, h6.H6_FP64, False),
                                               (262144, h6.H6_MIXED, True)])
 def test_device_loop_full_size_sync_block_against_oracle(n, precision, imf):
