@@ -18,13 +18,13 @@
 // targets share its group.
 //
 // Per block, three kernels in stream order:
-//   k_bl_predict  tile kind (large active sets) only: every particle
+//   k_bl_predict  tile kinds (active sets above 48) only: every particle
 //                 predicted to t_next into the predicted arrays.
 //   k_bl_eval     fixed grid; each workgroup takes (target group, source
 //                 slice) units and writes slice sums. Small active sets
 //                 predict their sources and targets on the fly from the state
 //                 (a pass over all particles would cost more than their
-//                 evaluation); the tile kind reads the predicted arrays.
+//                 evaluation); the tile kinds read the predicted arrays.
 //   k_bl_finish   compensated slice sums, corrector in place, list updates;
 //                 the last workgroup plans the next block.
 // Only the finishing workgroups (at most kFinGrid, fewer for small sets)
@@ -47,8 +47,9 @@ using namespace mixedbody;
 using namespace stepbody;
 
 constexpr int kSmall1Max = 16;   // active sets up to this size: one target per wave
-constexpr int kTileBlock = 64;   // tile kind: one wave, two targets per lane
-constexpr int kTileIpl = 2;
+constexpr int kTileBlock = 64;   // tile kinds: one-wave workgroups
+constexpr int kTileIpl = 2;      // targets per lane of tile kind 0
+constexpr int kTile1Max = 512;   // active sets up to this size: tile kind 2, one per lane
 constexpr int kFinThreads = 512;
 constexpr int kFinGrid = 128;    // finishing workgroups at most
 constexpr int kScanThreads = 256;
@@ -191,13 +192,14 @@ __device__ __forceinline__ int cdiv32(int a, int b) { return (a + b - 1) / b; }
 // Evaluation shape for n_act targets (32-bit arithmetic: one thread runs
 // it on the critical path). Source-parallel kinds (1: one target per wave,
 // 3: two), which predict on the fly: slices of at least 256 sources (4 per
-// lane), at most eval_grid waves in all. Tile kind 0 (128 targets per
-// one-wave workgroup, predicted arrays): as many slices as fit one round of
-// resident workgroups, down to one 64-source tile per slice (measured on
-// gfx950: for a few hundred targets, one-tile slices over the whole grid
-// beat fewer, longer ones by a third); with few slices per group, the
-// slice count that fills the last round of workgroups best. pc_pairs
-// bounds split * n_act.
+// lane), at most eval_grid waves in all. Tile kinds read the predicted
+// arrays. Kind 2 (up to kTile1Max targets; 64 per one-wave workgroup, one
+// per lane): the slice count from a small model of the time, below. Kind 0
+// (128 targets per workgroup, two per lane): as many slices as fit one
+// round of resident workgroups, down to one 64-source tile per slice; with
+// few slices per group, the slice count that fills the last round best.
+// The grid holds two waves per SIMD, which share its issue rate, so a round
+// of units is one unit per SIMD. pc_pairs bounds split * n_act.
 __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsigned pc_pairs) {
     int split, kind, groups;
     if (n_act <= kSmall2Max) {
@@ -206,6 +208,30 @@ __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsig
         split = (n + 255) >> 8;
         const int fit = eval_grid / groups;
         split = split < fit ? split : fit;
+    } else if (n_act <= kTile1Max) {
+        // time in source rows of one unit, for r units per SIMD (r = 1..6):
+        // rounds x slice length, a lone wave per SIMD issuing at about 3/4 of
+        // the rate of two, plus the slice sums (72 bytes per slice and
+        // target, written, read back and reduced: about 1/2400 row each)
+        kind = 2;
+        groups = cdiv32(n_act, kTileBlock);
+        const int simds = eval_grid / 2;
+        const int cap = (n + kTileBlock - 1) / kTileBlock;
+        int best_cost = 0x7fffffff;
+        split = 1;
+        for (int r = 1; r <= 6; ++r) {
+            int sp = r * simds / groups;
+            sp = sp < 1 ? 1 : (sp > cap ? cap : sp);
+            const int sl = cdiv32(cdiv32(n, sp), 64) * 64;
+            sp = cdiv32(n, sl);
+            const int units = groups * sp;
+            int cost = units <= simds ? sl + sl / 3 : cdiv32(units, simds) * sl;
+            cost += (int)(((unsigned)sp * (unsigned)n_act) / 2400u);
+            if (cost < best_cost) {
+                best_cost = cost;
+                split = sp;
+            }
+        }
     } else {
         kind = 0;
         groups = cdiv32(n_act, kTileBlock * kTileIpl);
@@ -215,10 +241,8 @@ __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsig
         if (split < 1) split = 1;
         if (split <= 16) {
             // few slices per group: the last round of units may leave SIMDs
-            // idle. The grid holds two waves per SIMD, which share its issue
-            // rate, so a round is one unit per SIMD, not per workgroup. Take
-            // the slice count in [split, 4 split] with the least rounds x
-            // slice length (ties: fewer slices).
+            // idle. Take the slice count in [split, 4 split] with the least
+            // rounds x slice length (ties: fewer slices).
             const int simds = eval_grid / 2;
             int best = split, best_cost = 0x7fffffff;
             const int hi = 4 * split < cap ? 4 * split : cap;
@@ -369,7 +393,7 @@ __device__ void plan_next(const LoopArgs &A, const LoopDesc *__restrict__ cur, c
 
 __global__ __launch_bounds__(256) void k_bl_predict(LoopArgs A, int64_t seq) {
     const LoopDesc *__restrict__ d = A.desc + (seq & 1);
-    if (d->n_act == 0 || d->kind != 0) return;
+    if (d->n_act == 0 || (d->kind != 0 && d->kind != 2)) return;
     const int64_t tn = d->t_next;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += gridDim.x * blockDim.x)
         predict_one(A.st, i, (double)(tn - A.st.t[i]) * kTick, A.pred);
@@ -395,17 +419,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     if ((int)blockIdx.x >= units) return;
     __shared__ RankTable rt;
     rank_table_from(&rt, h);
-    if (kind == 0) {
+    if (kind == 0 || kind == 2) {
         const ListPredSrc S{A, &rt};
         for (int u = blockIdx.x; u < units; u += gridDim.x) {
             const int g = u / split, sl = u - g * split;
-            if constexpr (MIXED)
-                mixed_tile_body<kTileBlock, kTileIpl, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len,
-                                                                out, slice_stride, g, sl);
-            else
-                eval_tile_body<2, kTileBlock, kTileIpl, SKIPSELF>(S, A.n, n_act, A.eps2,
-                                                                  slice_len, out, slice_stride, g,
-                                                                  sl);
+            if (kind == 0) {
+                if constexpr (MIXED)
+                    mixed_tile_body<kTileBlock, kTileIpl, SKIPSELF>(S, A.n, n_act, A.eps2,
+                                                                    slice_len, out, slice_stride,
+                                                                    g, sl);
+                else
+                    eval_tile_body<2, kTileBlock, kTileIpl, SKIPSELF>(S, A.n, n_act, A.eps2,
+                                                                      slice_len, out,
+                                                                      slice_stride, g, sl);
+            } else {
+                if constexpr (MIXED)
+                    mixed_tile_body<kTileBlock, 1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len,
+                                                             out, slice_stride, g, sl);
+                else
+                    eval_tile_body<2, kTileBlock, 1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len,
+                                                               out, slice_stride, g, sl);
+            }
         }
         return;
     }

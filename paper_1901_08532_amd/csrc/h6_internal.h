@@ -59,7 +59,8 @@ struct LoopDesc {
     int32_t n_act;           // active particles; 0 = nothing to do
     int32_t done;            // 1 once t_next would pass t_end
     int32_t invalid;         // set-up found a state off the block grid
-    int32_t kind;            // evaluation kind: 0 tile, 1 one target per wave, 3 two
+    int32_t kind;            // evaluation kind: 0 tile (two targets per lane), 2 tile (one),
+                             // 1 one target per wave, 3 two
     int32_t groups;          // target groups
     int32_t split;           // source slices
     int32_t slice_len;       // sources per slice
