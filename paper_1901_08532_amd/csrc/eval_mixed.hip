@@ -10,7 +10,7 @@
 //     small difference, not of the large coordinates);
 //   * acceleration differences, the reciprocal square root (v_rsq_f32 and
 //     one Newton step), alpha, beta and the pair terms are FP32;
-//   * the a/j/s sums are FP64: FP32 products are gathered over 64 sources,
+//   * the a/j/s sums are FP64: FP32 products are gathered over 8 sources,
 //     then added to FP64 accumulators, which are flushed into compensated
 //     (hi, lo) pairs once per tile as in the FP64 kernel.
 // The launch structure (LDS tiles of sources, target per lane, source

@@ -13,11 +13,13 @@ namespace mixedbody {
 // Far, massless padding source: contributes exactly zero; small enough that
 // its squared distance stays finite in FP32.
 constexpr double kPadPosMixed = 1.0e15;
-// Sources per FP32 partial sum before it joins the FP64 sums. Measured on
-// N = 262144 (power-law masses): 64 instead of 8 leaves the largest errors
-// against the oracle unchanged (a 5.4e-7, j 4.2e-6, s 3.4e-6; medians up by
-// 10-40%) and makes a mixed block-step interval about 5% faster.
-constexpr int kChunk = 64;
+// Sources per FP32 partial sum before it joins the FP64 sums. Longer
+// partial sums are cheaper (64 sources: a mixed block-step interval at
+// N = 262144 about 5% faster, the largest a/j/s errors against the oracle
+// unchanged) but their round-off dominates the energy error of fixed-step
+// runs: N = 4096, 8 time units, largest |dE/E| 1.8e-11 with 8 sources,
+// 3.5e-11 to 6.5e-11 with 16 to 64.
+constexpr int kChunk = 8;
 
 // Pair terms of order 2 in FP32, accumulated into acc[0..8] (FP32). Same
 // factorisation as the FP64 routine: A = m r/R^3, J = m w/R^3 with

@@ -3,8 +3,8 @@ arithmetic) against the FP64 oracle.
 
 Stated bound, per target particle (vector norms), on Plummer inputs with
 power-law masses: |F_mixed - F_oracle| / |F_oracle| <= 2e-5 (a), 5e-5 (j),
-2e-4 (s). This is about 10-25 times the largest error measured on such
-inputs (1.4e-6, 1.9e-6, 9.1e-6 at N = 4096), i.e. about 20 units of FP32
+2e-4 (s). This is about 10-20 times the largest error measured on such
+inputs (1.1e-6, 2.2e-6, 9.7e-6 at N = 4096), i.e. about 20 units of FP32
 rounding (2^-24) times the cancellation the sums carry. The errors carry no
 common bias (mean signed radial error below 1e-7), and the energy drift of
 a block-step run stays within twice the FP64 path's.
