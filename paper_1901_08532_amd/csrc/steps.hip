@@ -217,58 +217,92 @@ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e
     e = (a - (s - bp)) + (b - bp);
 }
 
-// Per particle: potential -m_i/2 sum_{j != i} m_j / sqrt(r^2+eps^2)
-// (compensated over source tiles), kinetic m v^2/2, angular momentum
-// m x cross v; workgroup sums as compensated (hi, lo) trees; the last
-// workgroup adds the workgroup sums in order. The sources are split into
-// gridDim.y slices of slice_len (whole tiles), so that enough workgroups
-// run; the potential is linear in the slices, and the kinetic and angular
-// momentum terms are taken by the first slice only.
+// Potential energy W = -sum over pairs i < j of m_i m_j / sqrt(r^2+eps^2),
+// each pair once: target block b (kEnergyThreads particles, one per thread)
+// meets the source tiles t >= b, and in its own tile only the sources
+// j > i. Blocks b and nb-1-b share a workgroup, so that every workgroup has
+// nb + 1 tiles of work (the middle block of an odd nb alone has fewer); the
+// tiles are cut into gridDim.y slices. Sums over a tile are plain, over
+// tiles compensated. Kinetic m v^2/2 and angular momentum m x cross v of
+// the workgroup's particles are taken by the first slice. Workgroup sums as
+// compensated (hi, lo) trees; the last workgroup adds them in order.
 __global__ __launch_bounds__(kEnergyThreads) void k_energy(h6_state st, int n, double eps2,
-                                                           int slice_len, double *partial,
-                                                           unsigned *counter, double *out) {
+                                                           double *partial, unsigned *counter,
+                                                           double *out) {
     __shared__ double4 tile[kEnergyThreads];  // x, y, z, m
     __shared__ double red_hi[5][kEnergyThreads];
     __shared__ double red_lo[5][kEnergyThreads];
     const int tid = threadIdx.x;
-    const int i = blockIdx.x * kEnergyThreads + tid;
-    const int ic = i < n ? i : n - 1;
-    const double xi0 = st.x[0][ic], xi1 = st.x[1][ic], xi2 = st.x[2][ic];
-    double phi_hi = 0.0, phi_lo = 0.0;
-    const int jb = (int)blockIdx.y * slice_len;
-    const int je = min(n, jb + slice_len);
-    for (int jt = jb; jt < je; jt += kEnergyThreads) {
+    const int nb = (n + kEnergyThreads - 1) / kEnergyThreads;
+    const int b0 = (int)blockIdx.x, b1 = nb - 1 - (int)blockIdx.x;
+    const bool two = b1 > b0;
+    const int nt0 = nb - b0, nt = nt0 + (two ? nb - b1 : 0);
+    const int vt0 = (int)(((int64_t)blockIdx.y * nt) / gridDim.y);
+    const int vt1 = (int)(((int64_t)(blockIdx.y + 1) * nt) / gridDim.y);
+    const int i0 = b0 * kEnergyThreads + tid, i1 = b1 * kEnergyThreads + tid;
+    const int c0 = i0 < n ? i0 : n - 1, c1 = i1 < n ? i1 : n - 1;
+    const double p0x = st.x[0][c0], p0y = st.x[1][c0], p0z = st.x[2][c0];
+    const double p1x = st.x[0][c1], p1y = st.x[1][c1], p1z = st.x[2][c1];
+    double phi0_hi = 0.0, phi0_lo = 0.0, phi1_hi = 0.0, phi1_lo = 0.0;
+    for (int vt = vt0; vt < vt1; ++vt) {
+        const bool first = vt < nt0;  // a tile of block b0 (else of b1)
+        const int b = first ? b0 : b1;
+        const int t = first ? b0 + vt : b1 + (vt - nt0);
         __syncthreads();
-        const int jj = jt + tid;
-        tile[tid] = jj < je ? make_double4(st.x[0][jj], st.x[1][jj], st.x[2][jj], st.m[jj])
-                            : make_double4(1.0e18, 1.0e18, 1.0e18, 0.0);
+        const int jj = t * kEnergyThreads + tid;
+        tile[tid] = jj < n ? make_double4(st.x[0][jj], st.x[1][jj], st.x[2][jj], st.m[jj])
+                           : make_double4(1.0e18, 1.0e18, 1.0e18, 0.0);
         __syncthreads();
+        const double xi0 = first ? p0x : p1x, xi1 = first ? p0y : p1y, xi2 = first ? p0z : p1z;
         double acc = 0.0;
+        if (t == b) {  // own tile: sources after the target only
 #pragma unroll 4
-        for (int q = 0; q < kEnergyThreads; ++q) {
-            const double4 r = tile[q];
-            const double dx = r.x - xi0, dy = r.y - xi1, dz = r.z - xi2;
-            double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
-            const bool self = (jt + q) == ic;
-            r2 = self ? 1.0 : r2;
-            const double mj = self ? 0.0 : r.w;
-            acc = fma(mj, rsqrt_f64(r2), acc);
+            for (int q = 0; q < kEnergyThreads; ++q) {
+                const double4 r = tile[q];
+                const double dx = r.x - xi0, dy = r.y - xi1, dz = r.z - xi2;
+                double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
+                const bool take = q > tid;
+                r2 = take ? r2 : 1.0;
+                acc = fma(take ? r.w : 0.0, rsqrt_f64(r2), acc);
+            }
+        } else {
+#pragma unroll 4
+            for (int q = 0; q < kEnergyThreads; ++q) {
+                const double4 r = tile[q];
+                const double dx = r.x - xi0, dy = r.y - xi1, dz = r.z - xi2;
+                const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
+                acc = fma(r.w, rsqrt_f64(r2), acc);
+            }
         }
         double s, e;
-        two_sum(phi_hi, acc, s, e);
-        phi_hi = s;
-        phi_lo += e;
+        if (first) {
+            two_sum(phi0_hi, acc, s, e);
+            phi0_hi = s;
+            phi0_lo += e;
+        } else {
+            two_sum(phi1_hi, acc, s, e);
+            phi1_hi = s;
+            phi1_lo += e;
+        }
     }
     double v[5] = {0, 0, 0, 0, 0};
-    if (i < n) {
-        const double m = st.m[i];
-        v[1] = -0.5 * m * (phi_hi + phi_lo);
-        if (blockIdx.y == 0) {
-            const double vx = st.v[0][i], vy = st.v[1][i], vz = st.v[2][i];
+    const bool has0 = i0 < n, has1 = two && i1 < n;
+    if (has0) v[1] = -st.m[i0] * (phi0_hi + phi0_lo);
+    if (has1) v[1] = fma(-st.m[i1], phi1_hi + phi1_lo, v[1]);
+    if (blockIdx.y == 0) {
+        if (has0) {
+            const double m = st.m[i0], vx = st.v[0][i0], vy = st.v[1][i0], vz = st.v[2][i0];
             v[0] = 0.5 * m * fma(vx, vx, fma(vy, vy, vz * vz));
-            v[2] = m * (xi1 * vz - xi2 * vy);
-            v[3] = m * (xi2 * vx - xi0 * vz);
-            v[4] = m * (xi0 * vy - xi1 * vx);
+            v[2] = m * (p0y * vz - p0z * vy);
+            v[3] = m * (p0z * vx - p0x * vz);
+            v[4] = m * (p0x * vy - p0y * vx);
+        }
+        if (has1) {
+            const double m = st.m[i1], vx = st.v[0][i1], vy = st.v[1][i1], vz = st.v[2][i1];
+            v[0] += 0.5 * m * fma(vx, vx, fma(vy, vy, vz * vz));
+            v[2] += m * (p1y * vz - p1z * vy);
+            v[3] += m * (p1z * vx - p1x * vz);
+            v[4] += m * (p1x * vy - p1y * vx);
         }
     }
 #pragma unroll
@@ -385,14 +419,13 @@ hipError_t launch_next_block(h6_ctx ctx, const h6_state *st, int n, int32_t *act
 
 hipError_t launch_energy(h6_ctx ctx, const h6_state *st, int n) {
     const int nb = (n + kEnergyThreads - 1) / kEnergyThreads;
-    const int tiles = nb;  // source tiles
-    // about four workgroups of four waves per compute unit
-    int split = std::max(1, std::min(kEnergyMaxSplit, (4 * ctx->n_cu + nb - 1) / nb));
-    split = std::min(split, tiles);
-    const int slice_len = ((tiles + split - 1) / split) * kEnergyThreads;
-    split = (n + slice_len - 1) / slice_len;
-    hipLaunchKernelGGL(k_energy, dim3(nb, split), dim3(kEnergyThreads), 0, ctx->stream, *st, n,
-                       ctx->eps2, slice_len, ctx->ered + 8, ctx->counters + 2, ctx->ered);
+    const int pairs = (nb + 1) / 2;  // workgroups per slice: blocks b and nb-1-b together
+    // about four workgroups of four waves per compute unit, at most one
+    // slice per tile of a workgroup's nb + 1
+    int split = std::max(1, std::min(kEnergyMaxSplit, (4 * ctx->n_cu + pairs - 1) / pairs));
+    split = std::min(split, nb + 1);
+    hipLaunchKernelGGL(k_energy, dim3(pairs, split), dim3(kEnergyThreads), 0, ctx->stream, *st, n,
+                       ctx->eps2, ctx->ered + 8, ctx->counters + 2, ctx->ered);
     return hipGetLastError();
 }
 

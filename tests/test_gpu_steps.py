@@ -229,8 +229,11 @@ def test_initial_steps_match_oracle():
     assert len(mism) <= 2
 
 
-def test_energy_matches_oracle():
-    n = 5000
+# 256-particle blocks: even and odd block counts (blocks b and nb-1-b share a
+# workgroup; the middle one of an odd count is alone), part-filled last
+# blocks, a single block, two particles, and the benchmark size
+@pytest.mark.parametrize("n", [5000, 4700, 256, 257, 2, 65536])
+def test_energy_matches_oracle(n):
     x, v, m = ics.plummer(n, 70)
     m = ics.salpeter_masses(n, 71)
     sysg = h6.System(x, v, m, EPS)
@@ -240,9 +243,14 @@ def test_energy_matches_oracle():
     assert abs(ep - wp) <= 1e-13 * abs(wp)
     scaleL = np.abs(m[:, None] * np.cross(x, v)).sum()
     assert np.abs(np.array(L) - wL).max() <= 1e-14 * scaleL
-    # a single particle has no potential energy
+
+
+def test_single_particle_has_no_potential_energy():
+    x, v, m = ics.plummer(8, 70)
     s1 = h6.System(x[:1], v[:1], m[:1], EPS)
-    assert s1.energy()[1] == 0.0
+    ek, ep, _ = s1.energy()
+    assert ep == 0.0
+    assert abs(ek - 0.5 * m[0] * (v[0] ** 2).sum()) <= 1e-15 * ek
 
 
 def test_shared_run_c1_matches_oracle():
