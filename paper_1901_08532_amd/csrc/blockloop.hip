@@ -217,7 +217,7 @@ __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsig
         groups = cdiv32(n_act, kTileBlock);
         const int simds = eval_grid / 2;
         const int cap = (n + kTileBlock - 1) / kTileBlock;
-        int best_cost = 0x7fffffff;
+        int64_t best_cost = INT64_MAX;
         split = 1;
         for (int r = 1; r <= 6; ++r) {
             int sp = r * simds / groups;
@@ -225,8 +225,9 @@ __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsig
             const int sl = cdiv32(cdiv32(n, sp), 64) * 64;
             sp = cdiv32(n, sl);
             const int units = groups * sp;
-            int cost = units <= simds ? sl + sl / 3 : cdiv32(units, simds) * sl;
-            cost += (int)(((unsigned)sp * (unsigned)n_act) / 2400u);
+            int64_t cost = units <= simds ? (int64_t)sl + sl / 3
+                                          : (int64_t)cdiv32(units, simds) * sl;
+            cost += (int64_t)sp * n_act / 2400;
             if (cost < best_cost) {
                 best_cost = cost;
                 split = sp;
@@ -244,12 +245,13 @@ __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsig
             // idle. Take the slice count in [split, 4 split] with the least
             // rounds x slice length (ties: fewer slices).
             const int simds = eval_grid / 2;
-            int best = split, best_cost = 0x7fffffff;
+            int best = split;
+            int64_t best_cost = INT64_MAX;
             const int hi = 4 * split < cap ? 4 * split : cap;
             for (int sp = split; sp <= hi; ++sp) {
                 const int sl = cdiv32(cdiv32(n, sp), 64) * 64;
                 const int units = groups * cdiv32(n, sl);
-                const int cost = cdiv32(units, simds) * sl;
+                const int64_t cost = (int64_t)cdiv32(units, simds) * sl;  // ~n_act n / 2^17
                 if (cost < best_cost) {
                     best_cost = cost;
                     best = sp;
