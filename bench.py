@@ -217,6 +217,7 @@ def main():
         psteps += st.particle_steps
         inter += st.interactions
         drift = max(drift, abs(e[0] + e[1] - E0) / abs(E0))
+        _log("step %d: %d blocks" % (k, st.blocks))  # after the step's own synchronising read
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = sysg.ctx.h6_profile_read()
