@@ -124,7 +124,12 @@ def counters(path, match, interactions):
         d = r["Dispatch_Id"]
         per[d][r["Counter_Name"]] = per[d].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
         meta[d] = (int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
-    key = "SQ_INSTS_VALU_FMA_F64" if any("SQ_INSTS_VALU_FMA_F64" in v for v in per.values()) else None
+    # rank dispatches by their FMA count (FP64, or FP32 for the mixed kernels)
+    tot = defaultdict(float)
+    for v in per.values():
+        for name in ("SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_FMA_F32"):
+            tot[name] += v.get(name, 0.0)
+    key = max(tot, key=tot.get) if tot else None
     top = sorted(per, key=lambda d: -per[d].get(key, 0.0) if key else 0.0)[:3]
     for d in top:
         c = per[d]
@@ -138,13 +143,15 @@ def counters(path, match, interactions):
             if name == "GRBM_GUI_ACTIVE" and dur > 0:
                 line += "   %.3f GHz" % (v / dur * 1e-9)
             print(line)
-        if key and all(k in c for k in ("SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64",
-                                        "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_TRANS_F64")):
-            ex = 64.0 * (2 * c["SQ_INSTS_VALU_FMA_F64"] + c["SQ_INSTS_VALU_ADD_F64"]
-                         + c["SQ_INSTS_VALU_MUL_F64"] + c["SQ_INSTS_VALU_TRANS_F64"])
-            print("executed FP64 flops per interaction (FMA 2, ADD/MUL/TRANS 1) = %.2f" % (ex / interactions))
+        for prec in ("F64", "F32"):
+            names = ["SQ_INSTS_VALU_%s_%s" % (op, prec) for op in ("FMA", "ADD", "MUL", "TRANS")]
+            if not all(k in c for k in names):
+                continue
+            ex = 64.0 * (2 * c[names[0]] + c[names[1]] + c[names[2]] + c[names[3]])
+            print("executed %s flops per interaction (FMA 2, ADD/MUL/TRANS 1) = %.2f"
+                  % (prec.replace("F", "FP"), ex / interactions))
             if dur > 0:
-                print("executed FP64 rate = %.2f TFLOP/s" % (ex / dur * 1e-12))
+                print("executed %s rate = %.2f TFLOP/s" % (prec.replace("F", "FP"), ex / dur * 1e-12))
 
 
 def main():
