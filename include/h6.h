@@ -395,10 +395,13 @@ int h6_potential(h6_ctx ctx, const h6_state *st, int64_t n, double *phi);
  */
 typedef struct {
     int order;      /* 2: per-step a/j/s; 1, 3: start-up passes */
-    int kind;       /* 0: LDS-tiled kernel; 1: source-parallel small-set kernel */
-    int block, ipl; /* launch shape of the instantiation */
+    int kind;       /* 0: LDS-tiled kernel; 1: source-parallel small-set kernel;
+                       2: evaluation kernel of the device-resident loop (its
+                       shape is chosen per block on the device) */
+    int block, ipl; /* launch shape of the instantiation (kind 2: 64, 2) */
     int precision;  /* H6_FP64, H6_MIXED, H6_EX or H6_SP */
-    int nact_log2;  /* bin: floor(log2(n_act)) of the launches in this record */
+    int nact_log2;  /* bin: floor(log2(n_act)) of the launches in this record;
+                       -1: device-loop launches of blocks with nothing due */
     int64_t launches;
     double interactions; /* sum of n_act * n over the launches */
     double kernel_ms;    /* sum of the event-measured kernel durations */
