@@ -231,6 +231,36 @@ def test_device_loop_evaluation_kind_boundaries(precision, n_act):
     _one_block_against_host_loop_and_oracle(20000, n_act, precision)
 
 
+@pytest.mark.parametrize("precision", [h6.H6_FP64, h6.H6_MIXED])
+def test_device_loop_two_clusters_full_activity_block(precision):
+    # the largest blocks of the two-cluster workload (2 x 524288, seeds 5 and
+    # 55, eps 1e-4) in the device loop's own launch shape: every particle on
+    # level 4 at t = 0, so the first block evaluates all 1048576 targets
+    # against all sources. Seeded a, j, s, c stand in for the start-up (any
+    # state is a valid input of the evaluation); sampled targets against the
+    # oracle on the loop's predicted arrays
+    x, v, m = ics.two_clusters(524288, 5, 55)
+    n = len(m)
+    rng = np.random.Generator(np.random.PCG64(555))
+    s = h6.System(x, v, m, EPS)
+    for k, scale in ((6, 1.0), (9, 0.1), (12, 0.01), (15, 0.001)):
+        s.S[k:k + 3] = torch.from_numpy(rng.normal(0.0, scale, (3, n))).to(DEV)
+    s.T[0].zero_()
+    s.T[1].fill_(1 << (TB - 4))
+    rc, st = s.run_blocks(1 << (TB - 4), 0.4, 4, 30, precision, check=False)
+    assert rc in (h6.H6_OK, h6.H6_EDTMIN)  # random derivatives may ask for tiny steps
+    assert (st.blocks, st.particle_steps) == (1, n)
+    P = s.P.cpu().numpy()
+    xp, vp, ap = P[0:3].T.copy(), P[3:6].T.copy(), P[6:9].T.copy()
+    idx = np.sort(rng.choice(n, 256, replace=False))
+    want = oracle.forces(xp, vp, m, EPS ** 2, a=ap, idx=idx, order=2)[:3]
+    bound = ({"a": 1e-12, "j": 1e-12, "s": 1e-12} if precision == h6.H6_FP64
+             else {"a": 2e-5, "j": 5e-5, "s": 2e-4})
+    for k, name in enumerate("ajs"):
+        err = vec_rel_err(s.field(name)[idx], want[k])
+        assert err.max() <= bound[name], (name, float(err.max()))
+
+
 @pytest.mark.parametrize("n,precision,imf", [(65536, h6.H6_FP64, False),
                                               (262144, h6.H6_MIXED, True)])
 def test_device_loop_full_size_sync_block_against_oracle(n, precision, imf):
