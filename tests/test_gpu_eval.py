@@ -13,7 +13,7 @@ import torch
 
 import oracle
 from paper_1901_08532_amd import h6
-from _gpu import gpu_evaluate, plummer_pred, vec_rel_err
+from _gpu import DEV, gpu_evaluate, plummer_pred, to_rows, vec_rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -144,3 +144,27 @@ def test_bad_arguments_rejected():
     assert ei.value.code == h6.H6_EINVAL
     with pytest.raises(h6.H6Error):
         ctx.h6_evaluate(P[:, :16].contiguous(), mt, None, 16, 7, F)
+
+
+def test_context_on_side_streams():
+    # a context made on one side stream, then moved to another with
+    # h6_set_stream, enqueues its work there: a copy ordered on that stream
+    # alone reads the finished sums, equal bit for bit to the default
+    # stream's (streams at the default priority)
+    n = 3000
+    x, v, a, m = plummer_pred(n, 31, EPS ** 2)
+    ref = gpu_evaluate(h6.Context(n, EPS), x, v, a, m)
+    P = to_rows(x, v, a)
+    mt = torch.from_numpy(np.ascontiguousarray(m)).to(DEV)
+    torch.cuda.synchronize()  # inputs complete before other streams read them
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    ctx = h6.Context(n, EPS, stream=s1)
+    for k, s in enumerate((s1, s2)):
+        if k:
+            ctx.set_stream(s)
+        with torch.cuda.stream(s):
+            F = torch.full((9, n), np.nan, dtype=torch.float64, device=DEV)
+            ctx.h6_evaluate(P, mt, None, n, h6.H6_FP64, F)
+            out = F.cpu().numpy()
+        for c in range(3):
+            assert np.array_equal(out[3 * c:3 * c + 3].T, ref[c]), (k, c)
