@@ -288,3 +288,42 @@ def test_device_loop_full_size_sync_block_against_oracle(n, precision, imf):
         got = s.field(name)[idx]
         err = vec_rel_err(got, want[k])
         assert err.max() <= bound[name], (name, float(err.max()))
+
+
+def test_two_contexts_run_concurrently_from_two_threads():
+    # distinct contexts are independent: two device-loop runs, each context
+    # on its own stream and driven from its own host thread, give bit for
+    # bit the state of the same runs made one after the other on the
+    # default stream
+    import threading
+
+    n = 4096
+    made = {}
+    for tag in ("a", "b", "a_ref", "b_ref"):
+        x, v, m = ics.plummer(n, 41 if tag.startswith("a") else 42)
+        s = h6.System(x, v, m, EPS)
+        s.startup(eta_s=0.1, lev_min=4, lev_max=30)
+        made[tag] = s
+    torch.cuda.synchronize()
+    for tag in ("a_ref", "b_ref"):
+        rc, _ = made[tag].run_blocks(SYNC, 0.4, 4, 30)
+        assert rc == h6.H6_OK
+    torch.cuda.synchronize()
+    streams = {"a": torch.cuda.Stream(), "b": torch.cuda.Stream()}
+    for tag, st in streams.items():
+        made[tag].ctx.set_stream(st)
+    rcs = {}
+
+    def run(tag):
+        rcs[tag] = made[tag].run_blocks(SYNC, 0.4, 4, 30)[0]
+
+    threads = [threading.Thread(target=run, args=(tag,)) for tag in streams]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    assert rcs == {"a": h6.H6_OK, "b": h6.H6_OK}
+    for tag in streams:
+        assert torch.equal(made[tag].T, made[tag + "_ref"].T), tag
+        assert torch.equal(made[tag].S, made[tag + "_ref"].S), tag
