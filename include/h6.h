@@ -164,8 +164,8 @@ int h6_predict_dt(h6_ctx ctx, const h6_state *st, int64_t n, double dt,
  * enum above; EX and SP accumulate per source slice in their own arithmetic,
  * and the slices are combined in FP64). n_act == 0 is a no-op.
  * Errors: H6_EINVAL (null pointer, n < 1, n > n_max, n_act < 0 or
- * n_act > n_max, bad precision). Active indices must lie in [0, n); they
- * are not checked on the device.
+ * n_act > n_max, n_act > n with active NULL, bad precision). Active
+ * indices must lie in [0, n); they are not checked on the device.
  */
 int h6_evaluate(h6_ctx ctx, const h6_pred *src, const double *m, int64_t n,
                 const int32_t *active, int64_t n_act, int precision,

@@ -168,3 +168,23 @@ def test_context_on_side_streams():
             out = F.cpu().numpy()
         for c in range(3):
             assert np.array_equal(out[3 * c:3 * c + 3].T, ref[c]), (k, c)
+
+
+def test_evaluate_rejects_bad_sizes_before_any_launch():
+    # sizes are validated on the host: n_act above n without an active
+    # list, negative n_act, n or n_act above the context's n_max
+    n = 100
+    x, v, a, m = plummer_pred(n, 33, EPS ** 2)
+    P = to_rows(x, v, a)
+    mt = torch.from_numpy(np.ascontiguousarray(m)).to(DEV)
+    F = torch.zeros((9, 2 * n), dtype=torch.float64, device=DEV)
+    ctx = h6.Context(2 * n, EPS)
+    for n_act in (n + 1, -1, 2 * n + 1):
+        with pytest.raises(h6.H6Error) as e:
+            ctx.h6_evaluate(P, mt, None, n_act, h6.H6_FP64, F)
+        assert e.value.code == h6.H6_EINVAL
+    small = h6.Context(n - 1, EPS)
+    with pytest.raises(h6.H6Error) as e:
+        small.h6_evaluate(P, mt, None, 1, h6.H6_FP64, F)
+    assert e.value.code == h6.H6_EINVAL
+    assert torch.count_nonzero(F).item() == 0  # nothing was written
