@@ -150,11 +150,6 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    if args.workload == "adjoint":
-        return run_adjoint(args)
-    args.n = 65536 if args.n is None else args.n
-    args.seed = 2 if args.seed is None else args.seed
-
     import numpy as np
     import torch
 
@@ -169,6 +164,10 @@ def main():
         torch.cuda.synchronize()
         _log("copy calibration: %d bytes" % nbytes)
         del src, dst
+    if args.workload == "adjoint":
+        return run_adjoint(args)
+    args.n = 65536 if args.n is None else args.n
+    args.seed = 2 if args.seed is None else args.seed
     n, eps, eta, lev_min, lev_max = args.n, 1e-4, 0.4, 4, 30
     prec = h6.H6_FP64 if args.precision == "fp64" else h6.H6_MIXED
     sync_ticks = 1 << (h6.TICK_BITS - lev_min)
@@ -386,15 +385,43 @@ VJP_COUNTER_FILE = os.path.join(ROOT, "profiles", "eval_vjp_valu_counters.md")
 ADJ_METRIC = "pair-sum passes x N^2 per second, forward sums and their vector-Jacobian products"
 
 
+VJP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eval_vjp_hbm_traffic.txt")
+VJP_SOURCES = ("adjoint.hip", "device_math.h")
+
+
+def _vjp_record():
+    """key = value lines of the VJP kernel's traffic record if it was taken
+    for the current VJP sources (the VALU counter summary was taken with
+    them too), else None."""
+    if not os.path.exists(VJP_TRAFFIC_FILE):
+        return None
+    fields = {}
+    for line in open(VJP_TRAFFIC_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in VJP_SOURCES:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return fields if fields.get("vjp_source_sha256") == h.hexdigest() else None
+
+
 def _vjp_flops_per_pair():
     """Executed FP64 flops per pair of the evaluation VJP kernel (FMA 2,
-    ADD/MUL/TRANS 1) from the committed counter summary, or None."""
-    if not os.path.exists(VJP_COUNTER_FILE):
+    ADD/MUL/TRANS 1) from the committed counter summary, or None once the
+    VJP sources changed since it was taken."""
+    if not os.path.exists(VJP_COUNTER_FILE) or _vjp_record() is None:
         return None
     for line in open(VJP_COUNTER_FILE):
         if line.startswith("executed FP64 flops per interaction"):
             return float(line.rsplit("=", 1)[1])
     return None
+
+
+def _vjp_traffic_per_launch():
+    rec = _vjp_record()
+    key = "hbm_bytes_per_launch_eval_vjp"
+    return float(rec[key]) if rec and key in rec else None
 
 
 def run_adjoint(args):
@@ -484,7 +511,7 @@ def run_adjoint(args):
         "peak": FP64_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": achieved / FP64_PEAK_TFLOPS if achieved is not None else None,
-        "traffic": None,
+        "traffic": _vjp_traffic_per_launch(),  # of the k_eval_vjp dispatch alone
         "kernel": "k_eval_vjp<2, 128, 0> + slice reduction (one h6_evaluate_vjp call)",
         "flops_per_pair": fpp,
         "flops_convention": "executed FP64 flops per pair from the VALU counters (FMA 2, ADD/MUL/TRANS 1)",

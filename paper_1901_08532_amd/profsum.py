@@ -10,7 +10,7 @@
       and the clock from GRBM_GUI_ACTIVE
 
   python -m paper_1901_08532_amd.profsum traffic <fetch counter_collection.csv>
-      <write counter_collection.csv> --copy-bytes B [--match SUBSTR]
+      <write counter_collection.csv> --copy-bytes B [--match SUBSTR] [--sources eval|vjp]
       HBM bytes per dispatch of each matching kernel from FETCH_SIZE and
       WRITE_SIZE (KiB per dispatch), each scaled by the ratio of the known
       bytes a plain device copy of B bytes moves to what the same counter
@@ -26,14 +26,16 @@ from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1901_08532_amd", "csrc")
-# the evaluation kernels' sources (the same list as bench.py checks)
+# the evaluation kernels' sources (the same list as bench.py checks), and
+# the evaluation VJP kernel's
 EVAL_SOURCES = ("eval_body.h", "eval_mixed_body.h", "device_math.h", "steps_body.h",
                 "blockloop.hip", "eval.hip", "eval_mixed.hip")
+VJP_SOURCES = ("adjoint.hip", "device_math.h")
 
 
-def eval_sources_sha256():
+def eval_sources_sha256(sources=EVAL_SOURCES):
     h = hashlib.sha256()
-    for f in EVAL_SOURCES:
+    for f in sources:
         h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()
 
@@ -76,7 +78,7 @@ def _counter_per_dispatch(path, counter):
     return by_kernel
 
 
-def traffic(fetch_csv, write_csv, copy_bytes, match=None):
+def traffic(fetch_csv, write_csv, copy_bytes, match=None, sources="eval"):
     fetch = _counter_per_dispatch(fetch_csv, "FETCH_SIZE")
     write = _counter_per_dispatch(write_csv, "WRITE_SIZE")
     # the calibration copy is the largest dispatch of a copy kernel in each run
@@ -89,7 +91,10 @@ def traffic(fetch_csv, write_csv, copy_bytes, match=None):
     print("copy_write_kib = %.1f" % cw)
     print("fetch_scale = %.6f" % f_scale)
     print("write_scale = %.6f" % w_scale)
-    print("eval_source_sha256 = %s" % eval_sources_sha256())
+    if sources == "vjp":
+        print("vjp_source_sha256 = %s" % eval_sources_sha256(VJP_SOURCES))
+    else:
+        print("eval_source_sha256 = %s" % eval_sources_sha256())
     for k in sorted(fetch):
         if match and match not in k:
             continue
@@ -104,6 +109,8 @@ def traffic(fetch_csv, write_csv, copy_bytes, match=None):
             tag = "bl_eval_fp64"
         elif "k_bl_eval<true, false>" in k:
             tag = "bl_eval_mixed"
+        elif "k_eval_vjp<2, 128, 0>" in k:
+            tag = "eval_vjp"
         else:
             tag = re.sub(r"\W+", "_", k)[:60]
         print("# %s: %d dispatches" % (k, len(fv)))
@@ -165,6 +172,8 @@ def main():
     b.add_argument("write_csv")
     b.add_argument("--copy-bytes", type=int, required=True)
     b.add_argument("--match")
+    b.add_argument("--sources", choices=("eval", "vjp"), default="eval",
+                   help="which kernels' sources the record's hash covers")
     c = sub.add_parser("counters")
     c.add_argument("csv")
     c.add_argument("--match", required=True)
@@ -175,7 +184,7 @@ def main():
     elif args.cmd == "counters":
         counters(args.csv, args.match, args.interactions)
     else:
-        traffic(args.fetch_csv, args.write_csv, args.copy_bytes, args.match)
+        traffic(args.fetch_csv, args.write_csv, args.copy_bytes, args.match, args.sources)
 
 
 if __name__ == "__main__":

@@ -26,12 +26,16 @@ def test_workload_choices_include_adjoint():
 
 
 def test_vjp_flop_count_is_read_from_the_counter_summary():
+    # read only while the VJP traffic record's source hash matches the
+    # current VJP sources (the counters were taken with those sources)
     sys.path.insert(0, ROOT)
     import bench
 
     f = bench._vjp_flops_per_pair()
-    if os.path.exists(bench.VJP_COUNTER_FILE):
+    t = bench._vjp_traffic_per_launch()
+    if os.path.exists(bench.VJP_COUNTER_FILE) and bench._vjp_record() is not None:
         assert f is not None and 100.0 < f < 1000.0
+        assert t is not None and t > 0
     else:
-        assert f is None
-    json.dumps({"f": f})
+        assert f is None and t is None
+    json.dumps({"f": f, "t": t})
