@@ -49,20 +49,6 @@ def _compile(src: str, extra=()) -> str:
     return obj
 
 
-def build_microbench(verbose: bool = False) -> str:
-    """Build the VALU issue-rate microbenchmark (measurement tool)."""
-    src = os.path.join(HERE, "microbench", "valu_rates.hip")
-    exe = os.path.join(HERE, "microbench", "valu_rates")
-    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-Wno-unused-result",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-o", exe, src]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError("hipcc failed for the microbenchmark:\n%s" % r.stderr)
-    if verbose:
-        print("built", exe)
-    return exe
-
-
 def build(verbose: bool = False, extra=()) -> str:
     """Compile every HIP source and link libh6.so; returns its path."""
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
@@ -80,7 +66,4 @@ def build(verbose: bool = False, extra=()) -> str:
 
 
 if __name__ == "__main__":
-    if "--microbench" in sys.argv:
-        build_microbench(verbose=True)
-    else:
-        build(verbose=True, extra=sys.argv[1:])
+    build(verbose=True, extra=sys.argv[1:])
