@@ -223,8 +223,9 @@ int h6_next_block(h6_ctx ctx, const h6_state *st, int64_t n,
  * One whole block step (synchronizes): h6_next_block, h6_predict of all
  * particles, h6_evaluate of the active ones, h6_correct. pred (length n)
  * and f, active (length >= n) are caller-owned work arrays.
- * Errors: as the calls it makes, plus the device flags (H6_EDTMIN,
- * H6_ENONFINITE) checked after the step.
+ * Errors: as the calls it makes. A step clamped at 2^-lev_max or a
+ * non-finite result raises a device flag that h6_check_status reports
+ * (H6_EDTMIN, H6_ENONFINITE); the step is taken either way.
  */
 int h6_block_step(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred,
                   const h6_force *f, int32_t *active, const h6_params *prm,
@@ -386,24 +387,30 @@ int h6_predict_vjp(h6_ctx ctx, h6_state *cot, int64_t n, const int64_t *t_old,
 int h6_potential(h6_ctx ctx, const h6_state *st, int64_t n, double *phi);
 
 /*
- * Measurement hook: while enabled, HIP events bracket every a/j/s
+ * Measurement hook: while enabled (on = 1), HIP events bracket every a/j/s
  * evaluation kernel the context launches (on its stream), and the event
  * durations are accumulated per kernel instantiation and per power-of-two
- * bin of the active-set size. Enabling clears the
- * records. h6_profile_read (synchronizes) copies up to max records to out
- * and sets *count. Errors: H6_EINVAL, H6_EHIP.
+ * bin of the active-set size. on = 2 also times the device-resident loop's
+ * predictor and finishing kernels of every block (records of kind 3 and 4,
+ * binned by the block's active count like its evaluation). on = 0 turns the
+ * hook off. Enabling clears the records. h6_profile_read (synchronizes)
+ * copies up to max records to out and sets *count.
+ * Errors: H6_EINVAL (on outside 0..2), H6_EHIP.
  */
 typedef struct {
     int order;      /* 2: per-step a/j/s; 1, 3: start-up passes */
     int kind;       /* 0: LDS-tiled kernel; 1: source-parallel small-set kernel;
                        2: evaluation kernel of the device-resident loop (its
-                       shape is chosen per block on the device) */
-    int block, ipl; /* launch shape of the instantiation (kind 2: 64, 2) */
+                       shape is chosen per block on the device); 3, 4: the
+                       loop's predictor and finishing kernels (on = 2) */
+    int block, ipl; /* launch shape of the instantiation (kind 2: 64, 2;
+                       kinds 3, 4: 0, 0) */
     int precision;  /* H6_FP64, H6_MIXED, H6_EX or H6_SP */
     int nact_log2;  /* bin: floor(log2(n_act)) of the launches in this record;
                        -1: device-loop launches of blocks with nothing due */
     int64_t launches;
-    double interactions; /* sum of n_act * n over the launches */
+    double interactions; /* sum of n_act * n over the launches (kinds 3, 4:
+                            those of the blocks they belong to) */
     double kernel_ms;    /* sum of the event-measured kernel durations */
 } h6_eval_timing;
 

@@ -148,14 +148,16 @@ hipError_t prof_end(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int order, const E
     int bin = 0;
     for (int64_t na = n_act; na > 1; na >>= 1) ++bin;
     const int key = timing_key(ctx, order, cfg.kind, cfg.block, cfg.ipl, precision, bin);
-    ctx->pending.push_back({e0, e1, key, interactions, -1, precision});
+    ctx->pending.push_back({e0, e1, key, interactions, -1, precision, 0});
     return hipSuccess;
 }
 
-// Device-loop evaluation launch: its active count is known only on the
-// device; the block log (n_act per block sequence number) resolves it.
-hipError_t prof_push_seq(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int precision, int64_t seq) {
-    ctx->pending.push_back({e0, e1, -1, 0.0, seq, precision});
+// Device-loop launch (kind 2 evaluation, 3 predictor, 4 finishing kernel):
+// its active count is known only on the device; the block log (n_act per
+// block sequence number) resolves it.
+hipError_t prof_push_seq(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int precision, int64_t seq,
+                         int kind) {
+    ctx->pending.push_back({e0, e1, -1, 0.0, seq, precision, kind});
     return hipSuccess;
 }
 
@@ -190,7 +192,8 @@ hipError_t prof_resolve(h6_ctx ctx) {
             const int64_t na = log[(size_t)(p.seq & ctx->bl_log_mask)];
             int bin = -1;  // empty block (nothing evaluated)
             for (int64_t q = na; q >= 1; q >>= 1) ++bin;
-            key = timing_key(ctx, 2, 2, 64, 2, p.precision, bin);
+            key = p.kind == 2 ? timing_key(ctx, 2, 2, 64, 2, p.precision, bin)
+                              : timing_key(ctx, 2, p.kind, 0, 0, p.precision, bin);
             inter = (double)na * (double)ctx->bl_n;
         }
         h6_eval_timing &t = ctx->timings[key];
@@ -775,6 +778,7 @@ int h6_init_forces_vjp(h6_ctx ctx, const h6_state *st, int64_t n, h6_state *cot)
 
 int h6_profile_enable(h6_ctx ctx, int on) {
     if (!ctx) return H6_EINVAL;
+    if (on < 0 || on > 2) return fail_arg(ctx, "bad profile level");
     H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
     H6_TRY(ctx, prof_resolve(ctx), "profile events");
     if (on && !ctx->bl_log) {
@@ -785,6 +789,7 @@ int h6_profile_enable(h6_ctx ctx, int on) {
     }
     ctx->timings.clear();
     ctx->prof = on != 0;
+    ctx->prof_level = on;
     return H6_OK;
 }
 

@@ -47,11 +47,19 @@ using namespace mixedbody;
 using namespace stepbody;
 
 constexpr int kSmall1Max = 16;   // active sets up to this size: one target per wave
+// The predictor runs first (sources from the predicted arrays) unless the
+// active set is below n / kPredPerSource: the source-parallel kinds then
+// predict their sources on the fly, which costs each of their waves the
+// prediction, the predictor a pass over all particles.
+constexpr int kPredPerSource = 262144;
 constexpr int kTileBlock = 64;   // tile kinds: one-wave workgroups
 constexpr int kTileIpl = 2;      // targets per lane of tile kind 0
 constexpr int kTile1Max = 512;   // active sets up to this size: tile kind 2, one per lane
 constexpr int kFinThreads = 512;
 constexpr int kFinGrid = 128;    // finishing workgroups at most
+constexpr int kFinSplitNarrow = 64;  // slices up to this: threads over targets; more: a wave each
+constexpr int kFinGroups = 7;    // wave-per-target reduction: lanes per component (9 x 7 of 64)
+constexpr int kStash = 2048;     // corrected particles a finishing workgroup holds for insertion
 constexpr int kScanThreads = 256;
 
 
@@ -103,7 +111,7 @@ struct RankTable {
 struct DescHead {
     int64_t t_next;
     unsigned long long sel;
-    int n_act, split, slice_len, groups, kind, L0, lv_hi;
+    int n_act, split, slice_len, groups, kind, L0, lv_hi, pred;
     int my_off, my_cnt;
 };
 __device__ __forceinline__ DescHead load_head(const LoopDesc *__restrict__ d) {
@@ -117,6 +125,7 @@ __device__ __forceinline__ DescHead load_head(const LoopDesc *__restrict__ d) {
     h.kind = d->kind;
     h.L0 = d->L0;
     h.lv_hi = d->lv_hi;
+    h.pred = d->pred;
     const int t = threadIdx.x < kLevels ? threadIdx.x : 0;
     h.my_off = d->off[t];
     h.my_cnt = d->cnt[t];
@@ -189,18 +198,43 @@ struct ListPredSrc {
 
 __device__ __forceinline__ int cdiv32(int a, int b) { return (a + b - 1) / b; }
 
-// Evaluation shape for n_act targets (32-bit arithmetic: one thread runs
-// it on the critical path). Source-parallel kinds (1: one target per wave,
-// 3: two), which predict on the fly: slices of at least 256 sources (4 per
+// Threads per target in the narrow finishing reduction (split <=
+// kFinSplitNarrow): the power of two covering the slices in fours.
+__device__ __forceinline__ int fin_seg(int split) {
+    int seg = 1;
+    while (4 * seg < split) seg <<= 1;
+    return seg;
+}
+// Waves per target in the wide finishing reduction (split > kFinSplitNarrow):
+// the power of two covering the slices in 256s, at most the workgroup's 8.
+__device__ __forceinline__ int fin_wpt(int split) {
+    int w = 1;
+    while (256 * w < split && w < kFinThreads / 64) w <<= 1;
+    return w;
+}
+// Targets per finishing workgroup round: kFinThreads / seg with few slices,
+// 8 / fin_wpt with more.
+__device__ __forceinline__ int fin_per_round(int split) {
+    return split > kFinSplitNarrow ? kFinThreads / 64 / fin_wpt(split)
+                                   : kFinThreads / fin_seg(split);
+}
+// Evaluation shape for n_act targets, chosen by one wave (every lane calls
+// it, lane 0 writes *d). Source-parallel kinds (1: one target per wave, 3:
+// two), which predict on the fly: slices of at least 256 sources (4 per
 // lane), at most eval_grid waves in all. Tile kinds read the predicted
-// arrays. Kind 2 (up to kTile1Max targets; 64 per one-wave workgroup, one
-// per lane): the slice count from a small model of the time, below. Kind 0
-// (128 targets per workgroup, two per lane): as many slices as fit one
-// round of resident workgroups, down to one 64-source tile per slice; with
-// few slices per group, the slice count that fills the last round best.
-// The grid holds two waves per SIMD, which share its issue rate, so a round
-// of units is one unit per SIMD. pc_pairs bounds split * n_act.
+// arrays: kind 2 (up to kTile1Max targets) has 64 targets per one-wave
+// workgroup (one per lane), kind 0 128 (two per lane). The grid holds two
+// waves per SIMD, which share its issue rate, so a round of units is one
+// unit per SIMD. For a tile kind lane r - 1 (r = 1..8) prices the shape
+// whose units fill r rounds: the time in source rows of one unit is rounds
+// x slice length (a lone unit per SIMD issuing at about 3/4 of the rate of
+// two), plus the slice sums (72 bytes per slice and target, written, read
+// back and reduced: about 1/2400 row of a 64-target unit each); the
+// cheapest shape wins, ties going to fewer slices. pc_pairs bounds
+// split * n_act.
 __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsigned pc_pairs) {
+    const int lane = threadIdx.x & 63;
+    const int pc = (int)(pc_pairs / (unsigned)n_act) > 0 ? (int)(pc_pairs / (unsigned)n_act) : 1;
     int split, kind, groups;
     if (n_act <= kSmall2Max) {
         kind = n_act <= kSmall1Max ? 1 : 3;
@@ -208,80 +242,51 @@ __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsig
         split = (n + 255) >> 8;
         const int fit = eval_grid / groups;
         split = split < fit ? split : fit;
-    } else if (n_act <= kTile1Max) {
-        // time in source rows of one unit, for r units per SIMD (r = 1..6):
-        // rounds x slice length, a lone wave per SIMD issuing at about 3/4 of
-        // the rate of two, plus the slice sums (72 bytes per slice and
-        // target, written, read back and reduced: about 1/2400 row each)
-        kind = 2;
-        groups = cdiv32(n_act, kTileBlock);
+        split = split < pc ? split : pc;
+        if (split < 1) split = 1;
+    } else {
+        const bool one = n_act <= kTile1Max;
+        kind = one ? 2 : 0;
+        const int tb = one ? kTileBlock : kTileBlock * kTileIpl;  // targets per unit
+        groups = cdiv32(n_act, tb);
         const int simds = eval_grid / 2;
-        const int cap = (n + kTileBlock - 1) / kTileBlock;
-        int64_t best_cost = INT64_MAX;
-        split = 1;
-        for (int r = 1; r <= 6; ++r) {
-            int sp = r * simds / groups;
+        const int cap = cdiv32(n, 64) < pc ? cdiv32(n, 64) : pc;
+        int sp = 1;
+        int64_t cost = INT64_MAX;
+        if (lane < 8) {
+            const int r = lane + 1;
+            sp = (int)((int64_t)r * simds / groups);
             sp = sp < 1 ? 1 : (sp > cap ? cap : sp);
             const int sl = cdiv32(cdiv32(n, sp), 64) * 64;
             sp = cdiv32(n, sl);
-            const int units = groups * sp;
-            int64_t cost = units <= simds ? (int64_t)sl + sl / 3
-                                          : (int64_t)cdiv32(units, simds) * sl;
-            cost += (int64_t)sp * n_act / 2400;
-            if (cost < best_cost) {
-                best_cost = cost;
-                split = sp;
-            }
+            const int64_t units = (int64_t)groups * sp;
+            cost = units <= simds ? (int64_t)sl + sl / 3 : ((units + simds - 1) / simds) * sl;
+            cost += (int64_t)sp * n_act / (2400 * (tb / kTileBlock));
+            // the finishing kernel's rounds, each about 10 us (42 rows of a
+            // 64-target unit)
+            const int fr = cdiv32(cdiv32(n_act, fin_per_round(sp)), kFinGrid);
+            cost += (int64_t)fr * 42 / (tb / kTileBlock);
         }
-    } else {
-        kind = 0;
-        groups = cdiv32(n_act, kTileBlock * kTileIpl);
-        split = eval_grid / groups;
-        const int cap = (n + kTileBlock - 1) / kTileBlock;
-        split = split < cap ? split : cap;
-        if (split < 1) split = 1;
-        if (split <= 16) {
-            // few slices per group: the last round of units may leave SIMDs
-            // idle. Take the slice count in [split, 4 split] with the least
-            // rounds x slice length (ties: fewer slices).
-            const int simds = eval_grid / 2;
-            int best = split;
-            int64_t best_cost = INT64_MAX;
-            const int hi = 4 * split < cap ? 4 * split : cap;
-            for (int sp = split; sp <= hi; ++sp) {
-                const int sl = cdiv32(cdiv32(n, sp), 64) * 64;
-                const int units = groups * cdiv32(n, sl);
-                const int64_t cost = (int64_t)cdiv32(units, simds) * sl;  // ~n_act n / 2^17
-                if (cost < best_cost) {
-                    best_cost = cost;
-                    best = sp;
-                }
-            }
-            split = best;
+        int64_t best = cost;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const int64_t o = __shfl_xor(best, off, 64);
+            best = o < best ? o : best;
         }
+        // candidates' slice counts grow with r: the lowest lane at the
+        // minimum has the fewest slices
+        const unsigned long long at = __ballot(lane < 8 && cost == best);
+        split = __shfl(sp, __builtin_ctzll(at), 64);
     }
-    const unsigned pc = pc_pairs / (unsigned)n_act;
-    if ((unsigned)split > pc) split = (int)pc;
-    if (split < 1) split = 1;
+    if (lane != 0) return;
     const int slice = cdiv32(cdiv32(n, split), 64) * 64;
+    d->pred = (int64_t)n_act * kPredPerSource >= n ? 1 : 0;
     d->kind = kind;
     d->groups = groups;
     d->slice_len = slice;
     d->split = cdiv32(n, slice);
 }
 
-// Lanes per target in the finishing reduction: the power of two covering
-// the slices, at most a wave; a wave sums 64 / seg targets at once.
-__device__ __forceinline__ int fin_seg(int split) {
-    int seg = 1;
-    while (seg < split && seg < 64) seg <<= 1;
-    return seg;
-}
-// Targets per finishing workgroup round and the number of finishing
-// workgroups with work, for a block of n_act targets in `split` slices.
-__device__ __forceinline__ int fin_per_round(int split) {
-    return (64 / fin_seg(split)) * (kFinThreads / 64);
-}
 __device__ __forceinline__ int fin_workers(int n_act, int split) {
     const int w = cdiv32(n_act, fin_per_round(split));
     return w < kFinGrid ? w : kFinGrid;
@@ -325,6 +330,7 @@ __device__ void plan_block(const LoopArgs &A, LoopDesc *d, const int *cnt, int64
     }
     const int n_act = __shfl(incl, 0, 64);
     if (!done && L >= L0 && L <= lv_hi) d->off[L] = incl - mine;
+    if (!done) launch_shape(d, A.n, n_act, A.eval_grid, A.pc_pairs);  // the whole wave
     if (L != 0) return;
     d->t_next = tn;
     d->lv_hi = lv_hi;
@@ -333,7 +339,6 @@ __device__ void plan_block(const LoopArgs &A, LoopDesc *d, const int *cnt, int64
     d->L0 = L0;
     d->done = done ? 1 : 0;
     if (!done) {
-        launch_shape(d, A.n, n_act, A.eval_grid, A.pc_pairs);
         blocks += 1;
         psteps += n_act;
     }
@@ -368,8 +373,8 @@ __device__ void plan_next(const LoopArgs &A, const LoopDesc *__restrict__ cur, c
                 if (solo) {
                     c = (int)solo->reb[L];
                 } else {
-                    c = (int)load_agent(&scr->reb[L]);
-                    store_agent(&scr->reb[L], 0u);
+                    c = (int)load_agent(&scr->reb[L][0]);
+                    store_agent(&scr->reb[L][0], 0u);
                 }
             } else if (L == L0 - 1) {
                 if (solo) {
@@ -395,7 +400,7 @@ __device__ void plan_next(const LoopArgs &A, const LoopDesc *__restrict__ cur, c
 
 __global__ __launch_bounds__(256) void k_bl_predict(LoopArgs A, int64_t seq) {
     const LoopDesc *__restrict__ d = A.desc + (seq & 1);
-    if (d->n_act == 0 || (d->kind != 0 && d->kind != 2)) return;
+    if (d->n_act == 0 || !d->pred) return;
     const int64_t tn = d->t_next;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += gridDim.x * blockDim.x)
         predict_one(A.st, i, (double)(tn - A.st.t[i]) * kTick, A.pred);
@@ -410,17 +415,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     if (n_act == 0) return;
     const int split = h.split, slice_len = h.slice_len, groups = h.groups;
     const int kind = h.kind;
-    // slice sums at partial[(k * 9 + c) * split + sl]: a target's slices are
-    // contiguous for the finishing reduction
+    // slice sums: with few slices (the finishing kernel gives each target a
+    // thread) at partial[(sl * 9 + c) * n_act + k], consecutive targets
+    // adjacent; with more (a wave per target) at partial[(k * 9 + c) * split
+    // + sl], a target's slices adjacent
+    const bool narrow = split <= kFinSplitNarrow;
     OutPtrs out;
 #pragma unroll
-    for (int c = 0; c < kMaxOut; ++c) out.p[c] = c < 9 ? A.partial + (int64_t)c * split : nullptr;
-    out.kstride = (int64_t)9 * split;
-    const int64_t slice_stride = 1;
+    for (int c = 0; c < kMaxOut; ++c)
+        out.p[c] = c < 9 ? A.partial + (int64_t)c * (narrow ? n_act : split) : nullptr;
+    out.kstride = narrow ? 1 : (int64_t)9 * split;
+    const int64_t slice_stride = narrow ? (int64_t)9 * n_act : 1;
     const int units = groups * split;
     if ((int)blockIdx.x >= units) return;
     __shared__ RankTable rt;
     rank_table_from(&rt, h);
+    // one workgroup-memory pool for the bodies (a tile, or the small sets'
+    // final reduction over 9 * 2 values per lane)
+    constexpr int kPool2 = 64 * 9;  // double2
+    static_assert(kPool2 >= kTileBlock * Traits<2>::NREC, "FP64 tile fits the pool");
+    static_assert(kPool2 * sizeof(double2) >= kTileBlock * sizeof(RecMixed), "mixed tile fits");
+    __shared__ double2 pool[kPool2];
+    double2 *tile = pool;
+    RecMixed *tile_m = reinterpret_cast<RecMixed *>(pool);
+    double *red = reinterpret_cast<double *>(pool);
     if (kind == 0 || kind == 2) {
         const ListPredSrc S{A, &rt};
         for (int u = blockIdx.x; u < units; u += gridDim.x) {
@@ -429,56 +447,70 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 if constexpr (MIXED)
                     mixed_tile_body<kTileBlock, kTileIpl, SKIPSELF>(S, A.n, n_act, A.eps2,
                                                                     slice_len, out, slice_stride,
-                                                                    g, sl);
+                                                                    g, sl, tile_m);
                 else
                     eval_tile_body<2, kTileBlock, kTileIpl, SKIPSELF>(S, A.n, n_act, A.eps2,
                                                                       slice_len, out,
-                                                                      slice_stride, g, sl);
+                                                                      slice_stride, g, sl, tile);
             } else {
                 if constexpr (MIXED)
                     mixed_tile_body<kTileBlock, 1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len,
-                                                             out, slice_stride, g, sl);
+                                                             out, slice_stride, g, sl, tile_m);
                 else
                     eval_tile_body<2, kTileBlock, 1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len,
-                                                               out, slice_stride, g, sl);
+                                                               out, slice_stride, g, sl, tile);
             }
         }
         return;
     }
-    const StateSrc S{A, &rt, h.t_next};
-    for (int u = blockIdx.x; u < units; u += gridDim.x) {
-        const int g = u / split, sl = u - g * split;
-        if (kind == 1) {
-            if constexpr (MIXED)
-                mixed_small_body<1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, out, slice_stride,
-                                              g, sl);
-            else
-                eval_small_body<1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, out, slice_stride,
-                                             g, sl);
-        } else {
-            if constexpr (MIXED)
-                mixed_small_body<2, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, out, slice_stride,
-                                              g, sl);
-            else
-                eval_small_body<2, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, out, slice_stride,
-                                             g, sl);
+    // small kinds: sources from the predicted arrays when the predictor ran,
+    // else predicted on the fly from the state
+    auto small = [&](const auto &S) {
+        for (int u = blockIdx.x; u < units; u += gridDim.x) {
+            const int g = u / split, sl = u - g * split;
+            if (kind == 1) {
+                if constexpr (MIXED)
+                    mixed_small_body<1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, out,
+                                                  slice_stride, g, sl, red);
+                else
+                    eval_small_body<1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, out,
+                                                 slice_stride, g, sl, red);
+            } else {
+                if constexpr (MIXED)
+                    mixed_small_body<2, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, out,
+                                                  slice_stride, g, sl, red);
+                else
+                    eval_small_body<2, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, out,
+                                                 slice_stride, g, sl, red);
+            }
         }
-    }
+    };
+    if (h.pred)
+        small(ListPredSrc{A, &rt});
+    else
+        small(StateSrc{A, &rt, h.t_next});
 }
 
-// Workgroup-aggregated list insertion: one slot reservation per level per
-// workgroup round, from the device counters, or from this workgroup's own
-// tally (solo) when it finishes the block alone. cur_cnt: the block's
-// level counts (LDS). Every thread calls it; valid marks the threads with a
-// particle. Ends with a barrier.
-__device__ void list_insert_wg(const LoopArgs &A, const RankTable *rt, const int *cur_cnt,
-                               Tally *solo, bool valid, int id, int lev) {
+// List insertion of the particles a finishing workgroup corrected (held in
+// LDS, ids and new levels): one slot reservation per level for all of them,
+// from the device counters (a line each), or from this workgroup's own
+// tally (solo) when it finishes the block alone. cur_cnt: the block's level
+// counts (LDS). Every thread calls it; it starts and ends with a barrier.
+__device__ void list_insert_stash(const LoopArgs &A, const RankTable *rt, const int *cur_cnt,
+                                  Tally *solo, const int32_t *st_id, const uint8_t *st_lev,
+                                  int nst) {
     __shared__ unsigned lcount[kLevels];
     __shared__ unsigned lbase[kLevels];
+    constexpr int kPer = kStash / kFinThreads;
+    __syncthreads();
     for (int L = threadIdx.x; L < kLevels; L += blockDim.x) lcount[L] = 0u;
     __syncthreads();
-    unsigned rank = 0;
-    if (valid) rank = atomicAdd(&lcount[lev], 1u);
+    unsigned rank[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int e = q * kFinThreads + threadIdx.x;
+        rank[q] = e < nst ? atomicAdd(&lcount[st_lev[e]], 1u) : 0u;
+    }
     __syncthreads();
     const int L0 = rt->L0;
     for (int L = threadIdx.x; L < kLevels; L += blockDim.x) {
@@ -493,30 +525,37 @@ __device__ void list_insert_wg(const LoopArgs &A, const RankTable *rt, const int
                     solo->app += c;
                 }
             } else {
-                lbase[L] = L >= L0 ? add_agent(&A.scr->reb[L], c)
+                lbase[L] = L >= L0 ? add_agent(&A.scr->reb[L][0], c)
                                    : (unsigned)cur_cnt[L] + add_agent(&A.scr->app, c);
             }
         }
     }
     __syncthreads();
-    if (valid) {
-        const int buf = (int)((rt->sel >> lev) & 1ull) ^ (lev >= L0 ? 1 : 0);
-        const unsigned slot = lbase[lev] + rank;
-        if (slot < (unsigned)A.n && lev >= A.lev_lo && lev < A.lev_lo + A.nl)
-            level_list(A, buf, lev)[slot] = id;
-        else
-            atomicOr(A.flags, kFlagLoop);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int e = q * kFinThreads + threadIdx.x;
+        if (e < nst) {
+            const int lev = st_lev[e];
+            const int buf = (int)((rt->sel >> lev) & 1ull) ^ (lev >= L0 ? 1 : 0);
+            const unsigned slot = lbase[lev] + rank[q];
+            if (slot < (unsigned)A.n && lev >= A.lev_lo && lev < A.lev_lo + A.nl)
+                level_list(A, buf, lev)[slot] = st_id[e];
+            else
+                atomicOr(A.flags, kFlagLoop);
+        }
     }
     __syncthreads();
 }
 
-// Neumaier step: s + comp += x.
-__device__ __forceinline__ void neumaier(double &s, double &comp, double x) {
-    const double t = s + x;
-    comp += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
-    s = t;
-}
-
+// Compensated slice sums, corrector, list updates, and (last workgroup) the
+// plan of the next block. Targets go in rounds of fin_per_round(split):
+// with few slices seg threads per target, four slices each (the slice sums
+// stored target-minor, so the loads are coalesced), merged in order; with more,
+// one wave per target whose lanes are (component, group) -- 9 x 7 -- each
+// summing every 7th slice of its component (stored slice-minor, loads of a
+// component coalesced), the 7 group sums then merged in order through LDS.
+// The corrected particles' list slots are reserved once per level for up
+// to kStash particles.
 __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t seq) {
     const LoopDesc *__restrict__ d = A.desc + (seq & 1);
     LoopDesc *dn = A.desc + ((seq + 1) & 1);
@@ -531,13 +570,16 @@ __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t s
         return;
     }
     const int split = h.split;
-    const int seg = fin_seg(split);
+    const bool wide = split > kFinSplitNarrow;
     const int per = fin_per_round(split);
     const int workers = fin_workers(n_act, split);
     if ((int)blockIdx.x >= workers) return;
     const int64_t tn = h.t_next;
     const bool solo = workers == 1;  // no other workgroup: tallies in LDS, no device atomics
     __shared__ double fs[kFinThreads * 9];
+    __shared__ double2 gsum[kFinThreads];  // wide: group sums, [wave][component * 7 + group]
+    __shared__ int32_t st_id[kStash];
+    __shared__ uint8_t st_lev[kStash];
     __shared__ RankTable rt;
     __shared__ int cur_cnt[kLevels];
     __shared__ Tally tally;
@@ -548,52 +590,104 @@ __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t s
     if (threadIdx.x == 0) tally.app = 0u;
     rank_table_from(&rt, h);  // ends with a barrier
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const double *__restrict__ part = A.partial;
+    int nst = 0;
     for (int k0 = blockIdx.x * per; k0 < n_act; k0 += workers * per) {
         const int nt = n_act - k0 < per ? n_act - k0 : per;
         const bool valid = tid < nt;
         int id = 0, lev = 0;
         OldState old{};
-        const bool reducer = w * (64 / seg) < nt;  // waves holding a target of the round
-        // seg lanes per target (contiguous slices: coalesced loads), the nine
-        // components' loads of four passes issued together, then a fixed
-        // butterfly within the segment
-        const double *__restrict__ part = A.partial;
-        const int r = w * (64 / seg) + lane / seg;  // target of this lane in the round
-        const int o = lane & (seg - 1);
-        const bool has = reducer && r < nt;
-        const int64_t base = (int64_t)(k0 + (has ? r : 0)) * 9 * split;
-        double x[4][9];
-        auto load_slices = [&](int sl0) {
+        if (wide) {
+            // waves wpt * r .. wpt * r + wpt - 1: target k0 + r; lane (c, g) of
+            // the p-th of them sums slices g', g' + G, ... of component c, with
+            // g' = 7 p + g and G = 7 wpt
+            const int wpt = kFinThreads / 64 / per;
+            const int r = w / wpt, pw = w - r * wpt;
+            const int c = lane / kFinGroups, g = lane - kFinGroups * (lane / kFinGroups);
+            const int gg = pw * kFinGroups + g, G = kFinGroups * wpt;
+            const bool has = r < nt && c < 9;
+            const double *__restrict__ pc =
+                part + ((int64_t)(k0 + (has ? r : 0)) * 9 + (has ? c : 0)) * split + gg;
+            const int nq = has && gg < split ? (split - gg + G - 1) / G : 0;
+            constexpr int U = 16;
+            double xa[U], xb[U];
+            auto load = [&](double *x, int i0) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int sl = sl0 + q * seg + o;
-                const bool in = has && sl < split;
-#pragma unroll
-                for (int c = 0; c < 9; ++c) x[q][c] = in ? part[base + c * split + sl] : 0.0;
+                for (int u = 0; u < U; ++u) x[u] = i0 + u < nq ? pc[(int64_t)G * (i0 + u)] : 0.0;
+            };
+            // the first slices, then the particle and its old state (list,
+            // then state: two dependent loads), all in flight together
+            const int nq_max = (split + G - 1) / G;
+            load(xa, 0);
+            if (valid) {
+                id = rank_to_particle(A, &rt, k0 + tid);
+                old = load_old<false>(A.st, id);
             }
-        };
-        // the first slices, then the particle and its old state (list, then
-        // state: two dependent loads), all in flight together
-        if (reducer) load_slices(0);
-        if (valid) {
-            id = rank_to_particle(A, &rt, k0 + tid);
-            old = load_old<false>(A.st, id);
-        }
-        if (reducer) {
-            double s[9], comp[9];
+            double hs = 0.0, hc = 0.0;
+            for (int i0 = 0; i0 < nq_max; i0 += 2 * U) {
+                if (i0 + U < nq_max) load(xb, i0 + U);
 #pragma unroll
-            for (int c = 0; c < 9; ++c) s[c] = comp[c] = 0.0;
-            for (int sl0 = 0; sl0 < split; sl0 += 4 * seg) {
-                if (sl0 != 0) load_slices(sl0);
+                for (int u = 0; u < U; ++u) two_sum_into(hs, hc, xa[u]);
+                if (i0 + U >= nq_max) break;
+                if (i0 + 2 * U < nq_max) load(xa, i0 + 2 * U);
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int c = 0; c < 9; ++c) neumaier(s[c], comp[c], x[q][c]);
+                for (int u = 0; u < U; ++u) two_sum_into(hs, hc, xb[u]);
             }
-            seg_comp_reduce_n<9>(s, comp, seg);  // totals in the segment's last lane
+            gsum[tid] = make_double2(hs, hc);
+            __syncthreads();
+            if (pw == 0 && r < nt && lane < 9) {
+                double ts = 0.0, tc = 0.0;
+                for (int q = 0; q < wpt; ++q)
 #pragma unroll
-            for (int c = 0; c < 9; ++c)
-                if (has && o == seg - 1) fs[r * 9 + c] = s[c] + comp[c];
+                    for (int gq = 0; gq < kFinGroups; ++gq) {
+                        const double2 e = gsum[(w + q) * 64 + lane * kFinGroups + gq];
+                        comp_merge(ts, tc, e.x, e.y);
+                    }
+                fs[r * 9 + lane] = ts + tc;
+            }
+        } else {
+            // thread tid = j * per + kl: slices 4j .. 4j + 3 of target k0 + kl
+            // (36 loads in flight; consecutive threads, consecutive targets:
+            // coalesced), the seg partial sums then merged in order
+            const int kl = tid % per, j = tid / per;
+            const bool mine = kl < nt;
+            const double *__restrict__ pk = part + (mine ? k0 + kl : 0);
+            const int64_t cs = n_act, ss = (int64_t)9 * n_act;
+            double x[36];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int c = 0; c < 9; ++c) {
+                    const int sl = 4 * j + q;
+                    x[q * 9 + c] = mine && sl < split ? pk[sl * ss + c * cs] : 0.0;
+                }
+            if (valid) {
+                id = rank_to_particle(A, &rt, k0 + tid);
+                old = load_old<false>(A.st, id);
+            }
+            double hs[9], hc[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) hs[c] = hc[c] = 0.0;
+#pragma unroll
+            for (int q = 0; q < 36; ++q) two_sum_into(hs[q % 9], hc[q % 9], x[q]);
+#pragma unroll
+            for (int c = 0; c < 9; ++c) fs[tid * 9 + c] = hs[c] + hc[c];
+            const int seg = kFinThreads / per;
+            if (seg > 1) {
+                __syncthreads();
+                if (tid < nt) {
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) {
+                        double ts = 0.0, tc = 0.0;
+                        for (int jj = 0; jj < seg; ++jj) two_sum_into(ts, tc, fs[(jj * per + tid) * 9 + c]);
+                        hs[c] = ts + tc;
+                    }
+                }
+                __syncthreads();
+                if (tid < nt)
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) fs[tid * 9 + c] = hs[c];
+            }
         }
         __syncthreads();
         if (valid) {
@@ -613,9 +707,17 @@ __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t s
             }
             A.st.t[id] = tn;
             A.st.dt[id] = (int64_t)1 << (kTickBits - lev);
+            st_id[nst + tid] = id;
+            st_lev[nst + tid] = (uint8_t)lev;
         }
-        list_insert_wg(A, &rt, cur_cnt, solo ? &tally : nullptr, valid, id, lev);
-        // (ends with a barrier: fs reusable)
+        nst += nt;
+        const bool last = k0 + workers * per >= n_act;
+        if (last || nst + per > kStash) {
+            list_insert_stash(A, &rt, cur_cnt, solo ? &tally : nullptr, st_id, st_lev, nst);
+            nst = 0;
+        } else {
+            __syncthreads();  // fs and gsum reusable
+        }
     }
     if (solo) {
         plan_next(A, d, cur_cnt, &tally, dn, seq);
@@ -629,7 +731,7 @@ __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t s
 
 __global__ void k_bl_setup_init(LoopArgs A) {
     LoopScratch *scr = A.scr;
-    for (int i = threadIdx.x; i < kLevels; i += blockDim.x) scr->reb[i] = 0u;
+    for (int i = threadIdx.x; i < kLevels; i += blockDim.x) scr->reb[i][0] = 0u;
     if (threadIdx.x == 0) {
         scr->done_fin = scr->app = scr->bad = 0u;
         scr->t_max = 0ull;
@@ -688,7 +790,7 @@ __global__ __launch_bounds__(kScanThreads) void k_bl_setup_scan(LoopArgs A) {
     if (good) rank = atomicAdd(&lcount[lev], 1u);
     __syncthreads();
     for (int L = threadIdx.x; L < kLevels; L += blockDim.x)
-        if (lcount[L] > 0) lbase[L] = add_agent(&A.scr->reb[L], lcount[L]);
+        if (lcount[L] > 0) lbase[L] = add_agent(&A.scr->reb[L][0], lcount[L]);
     __syncthreads();
     if (good) level_list(A, 0, lev)[lbase[lev] + rank] = i;
 }
@@ -702,10 +804,10 @@ __global__ void k_bl_setup_plan(LoopArgs A) {
     const unsigned long long tmax = scr->t_max, dmin = scr->due_min;
     const bool invalid = scr->bad != 0u || dmin <= tmax;
     for (int L = threadIdx.x; L < kLevels; L += blockDim.x) {
-        const int c = invalid ? 0 : (int)scr->reb[L];
+        const int c = invalid ? 0 : (int)scr->reb[L][0];
         s_cnt[L] = c;
         d->cnt[L] = c;
-        scr->reb[L] = 0u;
+        scr->reb[L][0] = 0u;
     }
     __syncthreads();
     if (invalid) {
@@ -740,17 +842,28 @@ hipError_t bl_setup(h6_ctx ctx, const LoopArgs &A) {
 }
 
 hipError_t bl_enqueue_block(h6_ctx ctx, const LoopArgs &A, int precision, int64_t seq) {
+    // with the measurement hook on, the events are those of the dispatches
+    // themselves (no separate marker packets in the stream)
+    const bool all = ctx->prof && ctx->prof_level >= 2;
+    auto events = [&](hipEvent_t *e0, hipEvent_t *e1, bool on) {
+        *e0 = *e1 = nullptr;
+        return on ? prof_events(ctx, e0, e1) : hipSuccess;
+    };
+    auto push = [&](hipEvent_t e0, hipEvent_t e1, bool on, int kind) {
+        if (!on) return hipSuccess;
+        hipError_t pe = hipGetLastError();
+        return pe != hipSuccess ? pe : prof_push_seq(ctx, e0, e1, precision, seq, kind);
+    };
+    hipEvent_t ev0, ev1;
+    hipError_t pe = events(&ev0, &ev1, all);
+    if (pe != hipSuccess) return pe;
     const int pgrid = ctx->n_cu > 1 ? ctx->n_cu / 2 : 1;
-    hipLaunchKernelGGL(k_bl_predict, dim3(pgrid), dim3(256), 0, ctx->stream, A, seq);
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (ctx->prof) {
-        hipError_t pe = prof_events(ctx, &ev0, &ev1);
-        if (pe != hipSuccess) return pe;
-    }
+    hipExtLaunchKernelGGL(k_bl_predict, dim3(pgrid), dim3(256), 0, ctx->stream, ev0, ev1, 0u, A,
+                          seq);
+    if ((pe = push(ev0, ev1, all, 3)) != hipSuccess) return pe;
+    if ((pe = events(&ev0, &ev1, ctx->prof)) != hipSuccess) return pe;
     const bool skip = self_pair_masked(A.eps2, precision);
     const bool mixed = precision == H6_MIXED;
-    // with the measurement hook on, the events are those of the dispatch
-    // itself (no separate marker packets in the stream)
 #define H6_BL_EVAL(M, S)                                                                         \
     hipExtLaunchKernelGGL((k_bl_eval<M, S>), dim3(A.eval_grid), dim3(64), 0, ctx->stream, ev0, \
                           ev1, 0u, A, seq)
@@ -760,13 +873,11 @@ hipError_t bl_enqueue_block(h6_ctx ctx, const LoopArgs &A, int precision, int64_
         if (skip) H6_BL_EVAL(false, true); else H6_BL_EVAL(false, false);
     }
 #undef H6_BL_EVAL
-    if (ctx->prof) {
-        hipError_t pe = hipGetLastError();
-        if (pe != hipSuccess) return pe;
-        pe = prof_push_seq(ctx, ev0, ev1, precision, seq);
-        if (pe != hipSuccess) return pe;
-    }
-    hipLaunchKernelGGL(k_bl_finish, dim3(kFinGrid), dim3(kFinThreads), 0, ctx->stream, A, seq);
+    if ((pe = push(ev0, ev1, ctx->prof, 2)) != hipSuccess) return pe;
+    if ((pe = events(&ev0, &ev1, all)) != hipSuccess) return pe;
+    hipExtLaunchKernelGGL(k_bl_finish, dim3(kFinGrid), dim3(kFinThreads), 0, ctx->stream, ev0,
+                          ev1, 0u, A, seq);
+    if ((pe = push(ev0, ev1, all, 4)) != hipSuccess) return pe;
     return hipGetLastError();
 }
 

@@ -137,4 +137,44 @@ __device__ __forceinline__ void seg_comp_reduce_n(double *s, double *c, int seg)
     if (seg >= 64) bcast_stage<NV, 0x143, 0xC>(s, c);  // row_bcast:31 into rows 2, 3
 }
 
+// Totals over the 64 lanes of a one-wave workgroup of NV values per lane,
+// through LDS instead of a butterfly of compensated merges (which costs NV
+// merges per stage and lane). On entry lds[v * 64 + lane] holds lane's value
+// v (a compensated pair already rounded to one double). Lane (v, g) -- G =
+// 64 / NV lanes per value -- sums every G-th lane's value v in lane order
+// into a compensated pair, and lane v merges the G pairs of value v in
+// order. Lane v < NV returns the total of value v, the other lanes 0; the
+// result does not depend on timing. lds: 64 * NV doubles of workgroup
+// memory (NV from 2 to 64); every thread of the workgroup calls it (it
+// contains barriers).
+template <int NV>
+__device__ __forceinline__ double wave_totals_lds(double *lds) {
+    static_assert(NV >= 2 && NV <= 64, "2 to 64 values per lane");
+    constexpr int G = 64 / NV;
+    const int lane = threadIdx.x & 63;
+    __syncthreads();
+    const int v = lane / G, g = lane - v * G;
+    double hs = 0.0, hc = 0.0;
+    if (v < NV) {
+#pragma unroll
+        for (int i = 0; i < (64 + G - 1) / G; ++i)
+            if (g + i * G < 64) two_sum_into(hs, hc, lds[v * 64 + g + i * G]);
+    }
+    __syncthreads();
+    if (v < NV) {
+        lds[2 * lane] = hs;
+        lds[2 * lane + 1] = hc;
+    }
+    __syncthreads();
+    double total = 0.0;
+    if (lane < NV) {
+        double ts = 0.0, tc = 0.0;
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            comp_merge(ts, tc, lds[2 * (lane * G + q)], lds[2 * (lane * G + q) + 1]);
+        total = ts + tc;
+    }
+    return total;
+}
+
 }  // namespace h6

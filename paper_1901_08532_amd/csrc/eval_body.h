@@ -97,14 +97,15 @@ struct PredSrc {
 
 // Body of the target-parallel LDS-tiled evaluation for the workgroup that
 // owns target block ib (BLOCK * IPL targets) and source slice sl.
+// tile: BLOCK * Traits<ORDER>::NREC double2 of workgroup memory.
 template <int ORDER, int BLOCK, int IPL, bool SKIPSELF, class SRC>
 __device__ __forceinline__ void eval_tile_body(const SRC &S, int n, int n_act, double eps2,
                                                int slice_len, const OutPtrs &out,
-                                               int64_t slice_stride, int ib, int sl) {
+                                               int64_t slice_stride, int ib, int sl,
+                                               double2 *tile) {
     using T = Traits<ORDER>;
     constexpr int NREC = T::NREC;
     constexpr int NACC = T::NACC;
-    __shared__ double2 tile[BLOCK * NREC];
     const int tid = threadIdx.x;
 
     // ---- targets: predicted state of particle active[k]
@@ -275,10 +276,12 @@ __device__ __forceinline__ void eval_tile_body(const SRC &S, int n, int n_act, d
 constexpr int kSmallPass = 4;
 constexpr int kSmallFlush = 4;
 
+// red: 64 * 9 * TPW doubles of workgroup memory (the final reduction).
 template <int TPW, bool SKIPSELF, class SRC>
 __device__ __forceinline__ void eval_small_body(const SRC &S, int n, int n_act, double eps2,
                                                 int slice_len, const OutPtrs &out,
-                                                int64_t slice_stride, int wave, int sl) {
+                                                int64_t slice_stride, int wave, int sl,
+                                                double *red) {
     constexpr int PASS = TPW == 1 ? kSmallPass : kSmallPass / 2;  // register budget
     const int lane = threadIdx.x & 63;
     const int jb = sl * slice_len;
@@ -355,24 +358,22 @@ __device__ __forceinline__ void eval_small_body(const SRC &S, int n, int n_act, 
                 }
         }
     }
-    double sv[TPW * 9], cv[TPW * 9];
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             two_sum_into(hi[t][q], lo[t][q], acc[t][q]);
-            sv[t * 9 + q] = hi[t][q];
-            cv[t * 9 + q] = lo[t][q];
+            red[(t * 9 + q) * 64 + lane] = hi[t][q] + lo[t][q];
         }
-    seg_comp_reduce_n<TPW * 9>(sv, cv, 64);  // totals in lane 63
+    // totals over the lanes: lane t * 9 + q holds component q of target t
+    const double total = wave_totals_lds<TPW * 9>(red);
     const int64_t soff = (int64_t)sl * slice_stride;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
         const int k = wave * TPW + t;
-        if (lane == 63 && k < n_act)
 #pragma unroll
-            for (int q = 0; q < 9; ++q)
-                out.p[q][soff + k * out.kstride] = sv[t * 9 + q] + cv[t * 9 + q];
+        for (int q = 0; q < 9; ++q)
+            if (lane == t * 9 + q && k < n_act) out.p[q][soff + k * out.kstride] = total;
     }
 }
 
@@ -383,8 +384,9 @@ __device__ __forceinline__ void eval_tile_body(const SrcPtrs &src,
                                                int n_act, double eps2, int slice_len,
                                                const OutPtrs &out, int64_t slice_stride, int ib,
                                                int sl) {
+    __shared__ double2 tile[BLOCK * Traits<ORDER>::NREC];
     eval_tile_body<ORDER, BLOCK, IPL, SKIPSELF>(PredSrc{src, active}, n, n_act, eps2, slice_len,
-                                                out, slice_stride, ib, sl);
+                                                out, slice_stride, ib, sl, tile);
 }
 
 template <int TPW, bool SKIPSELF>
@@ -393,8 +395,9 @@ __device__ __forceinline__ void eval_small_body(const SrcPtrs &src,
                                                 int n_act, double eps2, int slice_len,
                                                 const OutPtrs &out, int64_t slice_stride,
                                                 int wave, int sl) {
+    __shared__ double red[64 * 9 * TPW];
     eval_small_body<TPW, SKIPSELF>(PredSrc{src, active}, n, n_act, eps2, slice_len, out,
-                                   slice_stride, wave, sl);
+                                   slice_stride, wave, sl, red);
 }
 
 }  // namespace evalbody

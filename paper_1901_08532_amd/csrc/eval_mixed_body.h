@@ -65,11 +65,12 @@ struct alignas(16) RecMixed {
 };
 
 // Body for the workgroup owning target block ib and source slice sl.
+// tile: BLOCK records of workgroup memory.
 template <int BLOCK, int IPL, bool SKIPSELF, class SRC>
 __device__ __forceinline__ void mixed_tile_body(const SRC &S, int n, int n_act, double eps2,
                                                 int slice_len, const OutPtrs &out,
-                                                int64_t slice_stride, int ib, int sl) {
-    __shared__ RecMixed tile[BLOCK];
+                                                int64_t slice_stride, int ib, int sl,
+                                                RecMixed *tile) {
     const int tid = threadIdx.x;
     const float eps2f = (float)eps2;
 
@@ -173,10 +174,12 @@ __device__ __forceinline__ void mixed_tile_body(const SRC &S, int n, int n_act, 
 // kChunk sources per lane flushed into compensated FP64 pairs.
 constexpr int kPassM = 4;
 
+// red: 64 * 9 * TPW doubles of workgroup memory (the final reduction).
 template <int TPW, bool SKIPSELF, class SRC>
 __device__ __forceinline__ void mixed_small_body(const SRC &S, int n, int n_act, double eps2,
                                                  int slice_len, const OutPtrs &out,
-                                                 int64_t slice_stride, int wave, int sl) {
+                                                 int64_t slice_stride, int wave, int sl,
+                                                 double *red) {
     static_assert(kChunk % kPassM == 0, "flush on pass boundaries");
     const int lane = threadIdx.x & 63;
     const float eps2f = (float)eps2;
@@ -266,24 +269,22 @@ __device__ __forceinline__ void mixed_small_body(const SRC &S, int n, int n_act,
                 }
         }
     }
-    double sv[TPW * 9], cv[TPW * 9];
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             two_sum_into(hi[t][q], lo[t][q], (double)acc32[t][q]);
-            sv[t * 9 + q] = hi[t][q];
-            cv[t * 9 + q] = lo[t][q];
+            red[(t * 9 + q) * 64 + lane] = hi[t][q] + lo[t][q];
         }
-    seg_comp_reduce_n<TPW * 9>(sv, cv, 64);  // totals in lane 63
+    // totals over the lanes: lane t * 9 + q holds component q of target t
+    const double total = wave_totals_lds<TPW * 9>(red);
     const int64_t soff = (int64_t)sl * slice_stride;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
         const int k = wave * TPW + t;
-        if (lane == 63 && k < n_act)
 #pragma unroll
-            for (int q = 0; q < 9; ++q)
-                out.p[q][soff + k * out.kstride] = sv[t * 9 + q] + cv[t * 9 + q];
+        for (int q = 0; q < 9; ++q)
+            if (lane == t * 9 + q && k < n_act) out.p[q][soff + k * out.kstride] = total;
     }
 }
 
@@ -294,8 +295,9 @@ __device__ __forceinline__ void mixed_tile_body(const SrcPtrs &src,
                                                 int n_act, double eps2, int slice_len,
                                                 const OutPtrs &out, int64_t slice_stride, int ib,
                                                 int sl) {
+    __shared__ RecMixed tile[BLOCK];
     mixed_tile_body<BLOCK, IPL, SKIPSELF>(evalbody::PredSrc{src, active}, n, n_act, eps2,
-                                          slice_len, out, slice_stride, ib, sl);
+                                          slice_len, out, slice_stride, ib, sl, tile);
 }
 
 template <int TPW, bool SKIPSELF>
@@ -304,8 +306,9 @@ __device__ __forceinline__ void mixed_small_body(const SrcPtrs &src,
                                                  int n_act, double eps2, int slice_len,
                                                  const OutPtrs &out, int64_t slice_stride,
                                                  int wave, int sl) {
+    __shared__ double red[64 * 9 * TPW];
     mixed_small_body<TPW, SKIPSELF>(evalbody::PredSrc{src, active}, n, n_act, eps2, slice_len,
-                                    out, slice_stride, wave, sl);
+                                    out, slice_stride, wave, sl, red);
 }
 
 }  // namespace mixedbody

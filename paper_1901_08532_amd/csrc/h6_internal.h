@@ -66,16 +66,24 @@ struct LoopDesc {
     int32_t slice_len;       // sources per slice
     int32_t L0;              // lowest active level
     int32_t lv_hi;           // highest occupied level
+    int32_t pred;            // 1: the block's sources are predicted into the predicted arrays
     int32_t cnt[kLevels];    // particles per level
     int32_t off[kLevels];    // first active rank of level L (L >= L0)
 };
 
-// Counters of the loop (device, zero between blocks).
+// Counters of the loop (device, zero between blocks). Every counter that
+// many workgroups update in one block has a 128-byte line of its own:
+// device-scope atomics on one line serialise (about 11 ns each on this
+// GPU, measured), those on distinct lines proceed in parallel.
+constexpr int kLineU = 32;  // unsigned per 128-byte line
 struct LoopScratch {
     unsigned done_fin;             // finishing workgroups done
+    unsigned pad0[kLineU - 1];
     unsigned app;                  // particles appended to level L0 - 1
+    unsigned pad1[kLineU - 1];
+    unsigned reb[kLevels][kLineU]; // [L][0]: size of the rebuilt list of level L (set-up: fill)
     unsigned bad;                  // set-up: particles off the block grid
-    unsigned reb[kLevels];         // sizes of the rebuilt lists (set-up: fill)
+    unsigned pad2[kLineU - 1];
     unsigned long long t_max;      // set-up: latest particle time
     unsigned long long due_min;    // set-up: earliest t + dt
 };
@@ -145,8 +153,10 @@ struct h6_ctx_s {
         double interactions;
         int64_t seq;         // block sequence number (device loop)
         int precision;
+        int kind;            // device loop: 2 evaluation, 3 predictor, 4 finishing kernel
     };
     bool prof = false;
+    int prof_level = 0;  // 1: evaluation kernels; 2: also the device loop's other kernels
     std::vector<hipEvent_t> event_pool;
     std::vector<PendingTiming> pending;
     std::vector<h6_eval_timing> timings;
@@ -212,7 +222,8 @@ hipError_t prof_events(h6_ctx ctx, hipEvent_t *e0, hipEvent_t *e1);
 hipError_t prof_begin(h6_ctx ctx, hipEvent_t *e0, hipEvent_t *e1);
 hipError_t prof_end(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int order, const EvalConfig &cfg,
                     int precision, int64_t n_act, double interactions);
-hipError_t prof_push_seq(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int precision, int64_t seq);
+hipError_t prof_push_seq(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int precision, int64_t seq,
+                         int kind);
 hipError_t prof_resolve(h6_ctx ctx);  // stream must be idle
 
 // Device-resident block loop (blockloop.hip).

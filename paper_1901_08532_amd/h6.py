@@ -359,7 +359,10 @@ class Context:
         return lib().h6_check_status(self._h)
 
     def h6_profile_enable(self, on=True):
-        self._check(lib().h6_profile_enable(self._h, 1 if on else 0), "h6_profile_enable")
+        """on: False/0 off, True/1 evaluation kernels, 2 also the device
+        loop's predictor and finishing kernels."""
+        level = int(on) if not isinstance(on, bool) else (1 if on else 0)
+        self._check(lib().h6_profile_enable(self._h, level), "h6_profile_enable")
 
     def h6_profile_read(self):
         """List of dicts, one per evaluation-kernel instantiation launched."""

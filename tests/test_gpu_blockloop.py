@@ -274,11 +274,28 @@ def test_device_loop_full_size_sync_block_against_oracle(n, precision, imf):
         m = ics.salpeter_masses(n, 33)
     s = h6.System(x, v, m, EPS)
     s.startup(eta_s=0.1, lev_min=4, lev_max=30)
-    rc, st = s.run_blocks(1 << (h6.TICK_BITS - 4), 0.4, 4, 30, precision)
+    # every block before the sync time (t_end one tick short of it), then
+    # the sync block alone, from the state it starts from
+    rc, st = s.run_blocks(SYNC - 1, 0.4, 4, 30, precision)
     assert rc == h6.H6_OK and st.blocks > 100
-    assert bool((s.T[0] == (1 << (h6.TICK_BITS - 4))).all())
+    pre = {name: s.field(name) for name in ("x", "v", "a", "j", "s", "c")}
+    t_pre = s.T[0].cpu().numpy()
+    assert np.all(t_pre < SYNC)
+    rc, st = s.run_blocks(SYNC, 0.4, 4, 30, precision)
+    assert rc == h6.H6_OK and (st.blocks, st.particle_steps) == (1, n)
+    assert bool((s.T[0] == SYNC).all())
     P = s.P.cpu().numpy()
     xp, vp, ap = P[0:3].T.copy(), P[3:6].T.copy(), P[6:9].T.copy()
+    # the loop's predictor (all particles, each over its own interval)
+    # against the oracle's on the pre-block state: the sum of the absolute
+    # Taylor terms bounds the rounding of both
+    delta = (SYNC - t_pre) * 2.0 ** -TB
+    want_p = oracle.predict(pre["x"], pre["v"], pre["a"], pre["j"], pre["s"], pre["c"], delta)
+    D = delta[:, None]
+    order = ("x", "v", "a", "j", "s", "c")
+    for k, got_p in enumerate((xp, vp, ap)):
+        scale = sum(np.abs(pre[q]) * D ** (i - k) for i, q in enumerate(order) if i >= k)
+        assert np.all(np.abs(got_p - want_p[k]) <= 8e-16 * scale), k
     rng = np.random.Generator(np.random.PCG64(77))
     idx = np.sort(rng.choice(n, 256 if not imf else 1024, replace=False))
     want = oracle.forces(xp, vp, m, EPS ** 2, a=ap, idx=idx, order=2)[:3]

@@ -264,12 +264,12 @@ def test_shared_run_c1_matches_oracle():
     st = oracle.State(x, v, m, EPS ** 2)
     st.startup()
     st.shared_steps(1.0 / 1024, 100)
-    for name in ("x", "v"):
+    # every particle: the state after 100 steps and the a, j, s evaluated
+    # there (the largest errors measured: x 8.8e-15, v 1.6e-14, a 1.2e-13,
+    # j 2.2e-13, s 2.8e-13)
+    for name in ("x", "v", "a", "j", "s"):
         err = vec_rel_err(sysg.field(name), getattr(st, name))
-        assert err.max() < 1e-9, (name, err.max())
-    for name in ("a", "j", "s"):
-        err = vec_rel_err(sysg.field(name), getattr(st, name))
-        assert np.median(err) < 1e-9, (name, np.median(err))
+        assert err.max() < 1e-12, (name, err.max())
     e_g = sum(sysg.energy()[:2])
     e_o = sum(st.energy()[:2])
     assert abs(e_g - e_o) < 1e-10 * abs(e_o)
