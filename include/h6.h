@@ -387,6 +387,21 @@ int h6_predict_vjp(h6_ctx ctx, h6_state *cot, int64_t n, const int64_t *t_old,
 int h6_potential(h6_ctx ctx, const h6_state *st, int64_t n, double *phi);
 
 /*
+ * Gradient of the total energy (Eq. (1)'s E, as h6_energy computes it:
+ * E = sum_i m_i |v_i|^2 / 2 - sum_{i<j} m_i m_j / sqrt(r_ij^2 + eps^2))
+ * with respect to positions, velocities and masses, for energy losses:
+ * grad->x[c][i] = -g m_i a_i[c] (a the softened acceleration),
+ * grad->v[c][i] = g m_i v_i[c], grad->m[i] = g (|v_i|^2 / 2 + phi_i) with
+ * phi_i the potential of h6_potential. g is the cotangent of E: cot_e
+ * points to one double in device memory (so that a loss's gradient needs
+ * no host round trip), or is NULL for g = 1. Reads st->x, st->v, st->m;
+ * overwrites grad->x, grad->v, grad->m (other fields unused). O(n^2) pair
+ * work. Errors: H6_EINVAL.
+ */
+int h6_energy_vjp(h6_ctx ctx, const h6_state *st, int64_t n, const double *cot_e,
+                  h6_state *grad);
+
+/*
  * Measurement hook: while enabled (on = 1), HIP events bracket every a/j/s
  * evaluation kernel the context launches (on its stream), and the event
  * durations are accumulated per kernel instantiation and per power-of-two

@@ -217,21 +217,13 @@ class _SystemEnergy(torch.autograd.Function):
     @staticmethod
     def backward(ctx, ge):
         S, mm = ctx.saved_tensors
-        lc = ctx.lib_ctx
         n = mm.shape[0]
-        # dE/dx_i = -m_i a_i (a: softened acceleration); dE/dv_i = m_i v_i;
-        # dE/dm_i = |v_i|^2 / 2 + phi_i
-        P = torch.zeros((9, n), dtype=torch.float64, device=S.device)
-        P[0:6] = S[0:6]
-        F = torch.empty((9, n), dtype=torch.float64, device=S.device)
-        lc.h6_evaluate(P, mm, None, n, h6.H6_FP64, F)
-        phi = torch.empty(n, dtype=torch.float64, device=S.device)
-        lc.h6_potential(S, mm, phi)
-        v = S[3:6]
-        gx = (-mm * F[0:3]).T
-        gv = (mm * v).T
-        gm = 0.5 * (v * v).sum(0) + phi
-        return ge * gx, ge * gv, ge * gm, None
+        # dE/dx, dE/dv, dE/dm times the cotangent, all on the device (h6_energy_vjp)
+        GS = torch.empty((18, n), dtype=torch.float64, device=S.device)
+        gm = torch.empty(n, dtype=torch.float64, device=S.device)
+        ge = ge.detach().to(device=S.device, dtype=torch.float64).contiguous()
+        ctx.lib_ctx.h6_energy_vjp(S, mm, ge, GS, gm)
+        return GS[0:3].T, GS[3:6].T, gm, None
 
 
 def system_energy(x, v, m, lib_ctx: h6.Context):

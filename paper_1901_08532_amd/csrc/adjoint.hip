@@ -677,7 +677,67 @@ __global__ __launch_bounds__(kPotBlock) void k_potential(h6_state st, int n, dou
     if (i < n) phi[i] = -(hi + lo);
 }
 
+// Gradient of the total energy E = sum_i m_i |v_i|^2 / 2 - sum_{i<j} m_i m_j
+// (r_ij^2 + eps^2)^(-1/2) scaled by its cotangent g (one device double; NULL:
+// 1): dE/dx_i = -m_i a_i with a_i the softened acceleration, dE/dv_i =
+// m_i v_i, dE/dm_i = |v_i|^2 / 2 + phi_i with phi_i the potential. One target
+// per lane over LDS tiles of (x, m); phi and a share each pair's r^2 and
+// 1/sqrt, compensated per tile.
+__global__ __launch_bounds__(kPotBlock) void k_energy_vjp(h6_state st, int n, double eps2,
+                                                          const double *__restrict__ cot,
+                                                          h6_state out) {
+    __shared__ double4 tile[kPotBlock];
+    const int tid = threadIdx.x;
+    const int i = (int)blockIdx.x * kPotBlock + tid;
+    const int ic = i < n ? i : n - 1;
+    const double xi = st.x[0][ic], yi = st.x[1][ic], zi = st.x[2][ic];
+    double hi[4] = {0.0, 0.0, 0.0, 0.0}, lo[4] = {0.0, 0.0, 0.0, 0.0};  // phi, a
+    for (int jt = 0; jt < n; jt += kPotBlock) {
+        __syncthreads();
+        const int jj = jt + tid;
+        tile[tid] = jj < n ? make_double4(st.x[0][jj], st.x[1][jj], st.x[2][jj], st.m[jj])
+                           : make_double4(kPadPosVjp, kPadPosVjp, kPadPosVjp, 0.0);
+        __syncthreads();
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        const int cnt = min(kPotBlock, n - jt);
+        for (int q = 0; q < cnt; ++q) {
+            const double4 t = tile[q];
+            const double dx = t.x - xi, dy = t.y - yi, dz = t.z - zi;
+            const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
+            const bool self = jt + q == ic;
+            const double rinv = rsqrt_f64(self ? 1.0 : r2);
+            const double mr = (self ? 0.0 : t.w) * rinv;
+            const double mr3 = mr * (rinv * rinv);
+            acc[0] += mr;
+            acc[1] = fma(mr3, dx, acc[1]);
+            acc[2] = fma(mr3, dy, acc[2]);
+            acc[3] = fma(mr3, dz, acc[3]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) two_sum_into(hi[q], lo[q], acc[q]);
+    }
+    if (i >= n) return;
+    const double g = cot ? *cot : 1.0;
+    const double mi = st.m[i];
+    double vv = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double vc = st.v[c][i];
+        vv = fma(vc, vc, vv);
+        out.x[c][i] = -g * (mi * (hi[1 + c] + lo[1 + c]));
+        out.v[c][i] = g * (mi * vc);
+    }
+    out.m[i] = g * fma(0.5, vv, -(hi[0] + lo[0]));
+}
+
 }  // namespace
+
+hipError_t launch_energy_vjp(h6_ctx ctx, const h6_state *st, int n, const double *cot,
+                             h6_state *out) {
+    hipLaunchKernelGGL(k_energy_vjp, dim3((n + kPotBlock - 1) / kPotBlock), dim3(kPotBlock), 0,
+                       ctx->stream, *st, n, ctx->eps2, cot, *out);
+    return hipGetLastError();
+}
 
 hipError_t launch_eval_vjp(h6_ctx ctx, int order, const SrcPtrs &src, const double *const *cot,
                            int n, const OutPtrs &out, unsigned acc_mask) {

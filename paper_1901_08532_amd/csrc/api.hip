@@ -725,6 +725,17 @@ int h6_potential(h6_ctx ctx, const h6_state *st, int64_t n, double *phi) {
     return H6_OK;
 }
 
+int h6_energy_vjp(h6_ctx ctx, const h6_state *st, int64_t n, const double *cot_e,
+                  h6_state *grad) {
+    if (!ctx) return H6_EINVAL;
+    if (!st || !grad || !st->m || !grad->m) return fail_arg(ctx, "null array");
+    for (int c = 0; c < 3; ++c)
+        if (!st->x[c] || !st->v[c] || !grad->x[c] || !grad->v[c]) return fail_arg(ctx, "null array");
+    if (int rc = check_n(ctx, n)) return rc;
+    H6_TRY(ctx, launch_energy_vjp(ctx, st, (int)n, cot_e, grad), "energy gradient");
+    return H6_OK;
+}
+
 int h6_init_forces_vjp(h6_ctx ctx, const h6_state *st, int64_t n, h6_state *cot) {
     if (!ctx) return H6_EINVAL;
     if (!state_ok(st, false) || !state_ok(cot, false)) return fail_arg(ctx, "null array");

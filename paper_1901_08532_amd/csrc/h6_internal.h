@@ -212,6 +212,9 @@ hipError_t launch_correct_block_vjp(h6_ctx ctx, h6_state *cot, const int32_t *ac
 hipError_t launch_predict_block_vjp(h6_ctx ctx, h6_state *cot, int n, const int64_t *t_old,
                                     int64_t t_tick, const h6_pred *cp);
 hipError_t launch_potential(h6_ctx ctx, const h6_state *st, int n, double *phi);
+// Energy gradient (x, v, m of out), scaled by the device cotangent cot (NULL: 1).
+hipError_t launch_energy_vjp(h6_ctx ctx, const h6_state *st, int n, const double *cot,
+                             h6_state *out);
 
 int sched_blocks_for(int64_t n);
 // Measurement hook helpers (api.hip). prof_begin / prof_end bracket a

@@ -114,6 +114,8 @@ _SIGS = {
     "h6_predict_vjp": (C.c_int, [C.c_void_p, C.POINTER(h6_state), C.c_int64, C.c_void_p,
                                  C.c_int64, C.POINTER(h6_pred)]),
     "h6_potential": (C.c_int, [C.c_void_p, C.POINTER(h6_state), C.c_int64, C.c_void_p]),
+    "h6_energy_vjp": (C.c_int, [C.c_void_p, C.POINTER(h6_state), C.c_int64, C.c_void_p,
+                                C.POINTER(h6_state)]),
     "h6_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "h6_profile_read": (C.c_int, [C.c_void_p, C.POINTER(h6_eval_timing), C.c_int,
                                   C.POINTER(C.c_int)]),
@@ -349,6 +351,14 @@ class Context:
         st = make_state(S, m, None)
         return self._check(lib().h6_potential(self._h, C.byref(st), S.shape[1], _ptr(phi)),
                            "h6_potential")
+
+    def h6_energy_vjp(self, S, m, cot_e, GS, gm):
+        """Energy gradient: rows 0-5 of GS (x, v) and gm, scaled by the
+        0-d device tensor cot_e (None: 1)."""
+        st, gs = make_state(S, m, None), make_state(GS, gm, None)
+        ce = _ptr(cot_e) if cot_e is not None else None
+        return self._check(lib().h6_energy_vjp(self._h, C.byref(st), S.shape[1], ce, C.byref(gs)),
+                           "h6_energy_vjp")
 
     def h6_init_forces_vjp(self, S, m, CS, gm):
         st, cs = make_state(S, m, None), make_state(CS, gm, None)

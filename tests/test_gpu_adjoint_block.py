@@ -140,6 +140,32 @@ def test_system_energy_and_its_gradient():
         assert _rel(g.cpu().numpy(), r.numpy()) <= 1e-11
 
 
+@pytest.mark.parametrize("n,cot", [(1, None), (257, None), (1000, 2.5)])
+def test_energy_vjp_call_against_the_reference(n, cot):
+    # the ABI call itself: every gradient component on the device, scaled by
+    # a cotangent held in device memory (NULL: 1), against the autograd
+    # gradient of the torch reference energy (n = 257: a ragged tile)
+    x, v, m = ics.plummer(max(n, 2), 17 + n)
+    x, v, m = x[:n], v[:n], m[:n]
+    eps = 1e-3
+    ctx = h6.Context(n, eps)
+    S = torch.zeros((18, n), dtype=torch.float64, device=DEV)
+    S[0:3] = torch.from_numpy(np.ascontiguousarray(x.T)).to(DEV)
+    S[3:6] = torch.from_numpy(np.ascontiguousarray(v.T)).to(DEV)
+    mt = torch.from_numpy(np.ascontiguousarray(m)).to(DEV)
+    GS = torch.full((18, n), float("nan"), dtype=torch.float64, device=DEV)
+    gm = torch.full((n,), float("nan"), dtype=torch.float64, device=DEV)
+    ce = None if cot is None else torch.tensor(cot, dtype=torch.float64, device=DEV)
+    ctx.h6_energy_vjp(S, mt, ce, GS, gm)
+    xr, vr, mr = (torch.from_numpy(a).clone().requires_grad_(True) for a in (x, v, m))
+    rx, rv, rm = torch.autograd.grad(ar.energy(xr, vr, mr, eps * eps), (xr, vr, mr))
+    g = 1.0 if cot is None else cot
+    assert _rel(GS[0:3].T.cpu().numpy(), g * rx.numpy()) <= 1e-11
+    assert _rel(GS[3:6].T.cpu().numpy(), g * rv.numpy()) <= 1e-15
+    assert _rel(gm.cpu().numpy(), g * rm.numpy()) <= 1e-11
+    assert torch.isnan(GS[6:]).all()  # only x, v (and m) are written
+
+
 def _block_grads(ctx, x, v, m, t_end, loss_fn, **kw):
     xt, vt, mt = (t.requires_grad_(True) for t in _dev(x, v, m))
     xT, vT = hermite_block_run(xt, vt, mt, ctx, t_end, **kw)
