@@ -172,6 +172,28 @@ int h6_evaluate(h6_ctx ctx, const h6_pred *src, const double *m, int64_t n,
                 const h6_force *out);
 
 /*
+ * h6_evaluate for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same evaluation and arguments as h6_evaluate (and the same kernels),
+ * without a context: the softening eps and the stream (hipStream_t, NULL:
+ * the null stream) are passed in. The slice partial sums go to a fixed
+ * device scratch of H6_NOALLOC_SCRATCH_BYTES per GPU (32 MiB, held by
+ * every GPU the library runs on until the process ends); the call
+ * allocates nothing. Every call on a GPU shares that GPU's scratch, so
+ * calls that overlap on one GPU (other streams, other host threads) race:
+ * order them. n_act must not exceed H6_NOALLOC_SCRATCH_BYTES / 72 (466033;
+ * one slice of partial sums per target). The first call on a device looks
+ * up the scratch's address. Returns codes only (no context for
+ * h6_last_error). Errors: H6_EINVAL (null pointer, n < 1, n_act < 0 or
+ * above the limit, n_act > n with active NULL, bad precision, eps < 0 or
+ * not finite), H6_EHIP.
+ */
+#define H6_NOALLOC_SCRATCH_BYTES (32 << 20)
+int h6_evaluate_noalloc(void *hip_stream, double eps, const h6_pred *src,
+                        const double *m, int64_t n, const int32_t *active,
+                        int64_t n_act, int precision, const h6_force *out);
+
+/*
  * Corrector (Sec. 3, third stage) for a block: each active particle
  * i = active[k] is due at t_next = t[i] + dt[i]. Its x, v are corrected
  * to 6th order from a, j, s at both ends of the step (old ones in st,

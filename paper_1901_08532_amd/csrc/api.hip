@@ -4,11 +4,18 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "h6_internal.h"
 
 using namespace h6;
+
+// Scratch of the allocation-free evaluation (h6_evaluate_noalloc): one copy
+// per GPU the library runs on, held until the process ends. Host code uses
+// the per-device address from hipGetSymbolAddress, never the array's name
+// (a host-side stand-in that is no device address).
+static __device__ __align__(256) double scratch[H6_NOALLOC_SCRATCH_BYTES / sizeof(double)];
 
 namespace {
 
@@ -113,6 +120,16 @@ int read_flags(h6_ctx ctx) {
     if (h[0] & kFlagDtMin) return H6_EDTMIN;
     return H6_OK;
 }
+
+constexpr int64_t kNoAllocDoubles = (int64_t)H6_NOALLOC_SCRATCH_BYTES / (int64_t)sizeof(double);
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+double *g_noalloc_ptr[kNoAllocDevices];  // device address of scratch, per device
+int g_noalloc_cu[kNoAllocDevices];       // compute units, per device
+
+// Largest active set of h6_evaluate_noalloc: one slice of its partial sums
+// (9 doubles per target) fits the scratch.
+int64_t n_noalloc_max_act() { return kNoAllocDoubles / 9; }
 
 }  // namespace
 
@@ -350,6 +367,60 @@ int h6_evaluate(h6_ctx ctx, const h6_pred *src, const double *m, int64_t n, cons
            launch_eval(ctx, 2, precision, src_from_pred(src, m), (int)n, active, (int)n_act,
                        out_from_force(out), nullptr),
            "evaluate");
+    return H6_OK;
+}
+
+int h6_evaluate_noalloc(void *hip_stream, double eps, const h6_pred *src, const double *m,
+                        int64_t n, const int32_t *active, int64_t n_act, int precision,
+                        const h6_force *out) {
+    if (!pred_ok(src) || !m || !force_ok(out)) return H6_EINVAL;
+    if (n < 1 || n > kMaxParticles || n_act < 0 || n_act > n_noalloc_max_act()) return H6_EINVAL;
+    if (!active && n_act > n) return H6_EINVAL;
+    if (!precision_ok(precision) || !std::isfinite(eps) || eps < 0.0) return H6_EINVAL;
+    if (n_act == 0) return H6_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return H6_EHIP;
+    }
+    if (dev < 0 || dev >= kNoAllocDevices) return H6_EINVAL;
+    double *ptr = nullptr;
+    int n_cu = 0;
+    {
+        // set-up once per device, with that device current
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        if (!g_noalloc_ptr[dev]) {
+            void *p = nullptr;
+            int cu = 0;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p ||
+                hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) !=
+                    hipSuccess) {
+                (void)hipGetLastError();
+                return H6_EHIP;
+            }
+            g_noalloc_ptr[dev] = (double *)p;
+            g_noalloc_cu[dev] = cu > 0 ? cu : 256;
+        }
+        ptr = g_noalloc_ptr[dev];
+        n_cu = g_noalloc_cu[dev];
+    }
+    // a context on the stack whose partial-sum scratch is the device array
+    // (its string and vectors stay empty: nothing is allocated)
+    h6_ctx_s c;
+    c.n_max = n;
+    c.eps = eps;
+    c.eps2 = eps * eps;
+    c.stream = (hipStream_t)hip_stream;
+    c.device = dev;
+    c.n_cu = n_cu;
+    c.partial = ptr;
+    c.partial_cap = kNoAllocDoubles;
+    const hipError_t e = launch_eval(&c, 2, precision, src_from_pred(src, m), (int)n, active,
+                                     (int)n_act, out_from_force(out), nullptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return H6_EHIP;
+    }
     return H6_OK;
 }
 

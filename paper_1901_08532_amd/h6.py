@@ -114,6 +114,9 @@ _SIGS = {
     "h6_predict_vjp": (C.c_int, [C.c_void_p, C.POINTER(h6_state), C.c_int64, C.c_void_p,
                                  C.c_int64, C.POINTER(h6_pred)]),
     "h6_potential": (C.c_int, [C.c_void_p, C.POINTER(h6_state), C.c_int64, C.c_void_p]),
+    "h6_evaluate_noalloc": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(h6_pred), C.c_void_p,
+                                      C.c_int64, C.c_void_p, C.c_int64, C.c_int,
+                                      C.POINTER(h6_force)]),
     "h6_energy_vjp": (C.c_int, [C.c_void_p, C.POINTER(h6_state), C.c_int64, C.c_void_p,
                                 C.POINTER(h6_state)]),
     "h6_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
