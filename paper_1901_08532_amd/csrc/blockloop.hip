@@ -18,13 +18,14 @@
 // targets share its group.
 //
 // Per block, three kernels in stream order:
-//   k_bl_predict  tile kinds (active sets above 48) only: every particle
-//                 predicted to t_next into the predicted arrays.
+//   k_bl_predict  every particle predicted to t_next into the predicted
+//                 arrays (measured on this GPU: even for one or two active
+//                 particles at N = 65536 this pass plus an evaluation that
+//                 reads predicted sources is faster than predicting each
+//                 source in every evaluation wave that reads it).
 //   k_bl_eval     fixed grid; each workgroup takes (target group, source
-//                 slice) units and writes slice sums. Small active sets
-//                 predict their sources and targets on the fly from the state
-//                 (a pass over all particles would cost more than their
-//                 evaluation); the tile kinds read the predicted arrays.
+//                 slice) units and writes slice sums, reading sources and
+//                 targets from the predicted arrays.
 //   k_bl_finish   compensated slice sums, corrector in place, list updates;
 //                 the last workgroup plans the next block.
 // Only the finishing workgroups (at most kFinGrid, fewer for small sets)
@@ -47,11 +48,6 @@ using namespace mixedbody;
 using namespace stepbody;
 
 constexpr int kSmall1Max = 16;   // active sets up to this size: one target per wave
-// The predictor runs first (sources from the predicted arrays) unless the
-// active set is below n / kPredPerSource: the source-parallel kinds then
-// predict their sources on the fly, which costs each of their waves the
-// prediction, the predictor a pass over all particles.
-constexpr int kPredPerSource = 262144;
 constexpr int kTileBlock = 64;   // tile kinds: one-wave workgroups
 constexpr int kTileIpl = 2;      // targets per lane of tile kind 0
 constexpr int kTile1Max = 512;   // active sets up to this size: tile kind 2, one per lane
@@ -111,7 +107,7 @@ struct RankTable {
 struct DescHead {
     int64_t t_next;
     unsigned long long sel;
-    int n_act, split, slice_len, groups, kind, L0, lv_hi, pred;
+    int n_act, split, slice_len, groups, kind, L0, lv_hi;
     int my_off, my_cnt;
 };
 __device__ __forceinline__ DescHead load_head(const LoopDesc *__restrict__ d) {
@@ -125,7 +121,6 @@ __device__ __forceinline__ DescHead load_head(const LoopDesc *__restrict__ d) {
     h.kind = d->kind;
     h.L0 = d->L0;
     h.lv_hi = d->lv_hi;
-    h.pred = d->pred;
     const int t = threadIdx.x < kLevels ? threadIdx.x : 0;
     h.my_off = d->off[t];
     h.my_cnt = d->cnt[t];
@@ -161,23 +156,8 @@ __device__ __forceinline__ int rank_to_particle(const LoopArgs &A, const RankTab
     return id;
 }
 
-// Source/target policies of the evaluation bodies; targets through the
-// level lists. StateSrc predicts from the state to t_next on the fly,
-// ListPredSrc reads the predicted arrays.
-struct StateSrc {
-    LoopArgs A;
-    const RankTable *rt;
-    int64_t t_next;
-    __device__ __forceinline__ int target(int k) const { return rank_to_particle(A, rt, k); }
-    template <int ORDER>
-    __device__ __forceinline__ void get(int p, double *x, double *v, double *a, double *j) const {
-        static_assert(ORDER == 2, "block steps evaluate a, j, s");
-        predict_vals(A.st, p, (double)(t_next - A.st.t[p]) * kTick, x, v, a);
-        j[0] = j[1] = j[2] = 0.0;
-    }
-    __device__ __forceinline__ double mass(int p) const { return A.st.m[p]; }
-};
-
+// Source/target policy of the evaluation bodies: targets through the level
+// lists, sources and targets from the predicted arrays.
 struct ListPredSrc {
     LoopArgs A;
     const RankTable *rt;
@@ -220,9 +200,8 @@ __device__ __forceinline__ int fin_per_round(int split) {
 }
 // Evaluation shape for n_act targets, chosen by one wave (every lane calls
 // it, lane 0 writes *d). Source-parallel kinds (1: one target per wave, 3:
-// two), which predict on the fly: slices of at least 256 sources (4 per
-// lane), at most eval_grid waves in all. Tile kinds read the predicted
-// arrays: kind 2 (up to kTile1Max targets) has 64 targets per one-wave
+// two): slices of at least 256 sources (4 per lane), at most eval_grid
+// waves in all. Tile kinds: kind 2 (up to kTile1Max targets) has 64 targets per one-wave
 // workgroup (one per lane), kind 0 128 (two per lane). The grid holds two
 // waves per SIMD, which share its issue rate, so a round of units is one
 // unit per SIMD. For a tile kind lane r - 1 (r = 1..8) prices the shape
@@ -280,7 +259,6 @@ __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsig
     }
     if (lane != 0) return;
     const int slice = cdiv32(cdiv32(n, split), 64) * 64;
-    d->pred = (int64_t)n_act * kPredPerSource >= n ? 1 : 0;
     d->kind = kind;
     d->groups = groups;
     d->slice_len = slice;
@@ -400,7 +378,7 @@ __device__ void plan_next(const LoopArgs &A, const LoopDesc *__restrict__ cur, c
 
 __global__ __launch_bounds__(256) void k_bl_predict(LoopArgs A, int64_t seq) {
     const LoopDesc *__restrict__ d = A.desc + (seq & 1);
-    if (d->n_act == 0 || !d->pred) return;
+    if (d->n_act == 0) return;
     const int64_t tn = d->t_next;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += gridDim.x * blockDim.x)
         predict_one(A.st, i, (double)(tn - A.st.t[i]) * kTick, A.pred);
@@ -449,23 +427,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                                                                     slice_len, out, slice_stride,
                                                                     g, sl, tile_m);
                 else
-                    eval_tile_body<2, kTileBlock, kTileIpl, SKIPSELF>(S, A.n, n_act, A.eps2,
-                                                                      slice_len, out,
-                                                                      slice_stride, g, sl, tile);
+                    eval_tile_body<2, kTileBlock, kTileIpl, SKIPSELF, false>(
+                        S, A.n, n_act, A.eps2, slice_len, out, slice_stride, g, sl, tile);
             } else {
                 if constexpr (MIXED)
                     mixed_tile_body<kTileBlock, 1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len,
                                                              out, slice_stride, g, sl, tile_m);
                 else
-                    eval_tile_body<2, kTileBlock, 1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len,
-                                                               out, slice_stride, g, sl, tile);
+                    eval_tile_body<2, kTileBlock, 1, SKIPSELF, true>(
+                        S, A.n, n_act, A.eps2, slice_len, out, slice_stride, g, sl, tile);
             }
         }
         return;
     }
-    // small kinds: sources from the predicted arrays when the predictor ran,
-    // else predicted on the fly from the state
-    auto small = [&](const auto &S) {
+    {
+        const ListPredSrc S{A, &rt};
         for (int u = blockIdx.x; u < units; u += gridDim.x) {
             const int g = u / split, sl = u - g * split;
             if (kind == 1) {
@@ -484,11 +460,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                                                  slice_stride, g, sl, red);
             }
         }
-    };
-    if (h.pred)
-        small(ListPredSrc{A, &rt});
-    else
-        small(StateSrc{A, &rt, h.t_next});
+    }
 }
 
 // List insertion of the particles a finishing workgroup corrected (held in
@@ -547,6 +519,62 @@ __device__ void list_insert_stash(const LoopArgs &A, const RankTable *rt, const 
     __syncthreads();
 }
 
+// Wide finishing reduction of one round (targets k0 .. k0 + nt - 1, nt <=
+// 8 / WPT): waves WPT r .. WPT r + WPT - 1 take target k0 + r; lane (c, g)
+// of the p-th of them sums slices g', g' + G, ... of component c (g' = 7 p
+// + g, G = 7 WPT) into a compensated pair, and lane c of the first wave
+// merges the 7 WPT pairs in order into fs[r * 9 + c]. particle() issues the
+// correcting threads' own loads after the first slices'. Every thread
+// calls it (it contains a barrier).
+template <int WPT, class PARTICLE>
+__device__ __forceinline__ void fin_wide_sums(const double *__restrict__ part, int k0, int nt,
+                                              int split, double2 *gsum, double *fs,
+                                              PARTICLE particle) {
+    constexpr int G = kFinGroups * WPT;
+    constexpr int U = 16;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int r = w / WPT, pw = w % WPT;
+    const int c = lane / kFinGroups, g = lane % kFinGroups;
+    const int gg = pw * kFinGroups + g;
+    const bool has = r < nt && c < 9;
+    const double *__restrict__ pc =
+        part + ((int64_t)(k0 + (has ? r : 0)) * 9 + (has ? c : 0)) * split + gg;
+    const int nq = has && gg < split ? (split - gg + G - 1) / G : 0;
+    double xa[U], xb[U];
+    auto load = [&](double *x, int i0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = i0 + u < nq ? pc[G * (i0 + u)] : 0.0;
+    };
+    // the first slices, then the particle and its old state (list, then
+    // state: two dependent loads), all in flight together
+    const int nq_max = (split + G - 1) / G;
+    load(xa, 0);
+    particle();
+    double hs = 0.0, hc = 0.0;
+    for (int i0 = 0; i0 < nq_max; i0 += 2 * U) {
+        if (i0 + U < nq_max) load(xb, i0 + U);
+#pragma unroll
+        for (int u = 0; u < U; ++u) two_sum_into(hs, hc, xa[u]);
+        if (i0 + U >= nq_max) break;
+        if (i0 + 2 * U < nq_max) load(xa, i0 + 2 * U);
+#pragma unroll
+        for (int u = 0; u < U; ++u) two_sum_into(hs, hc, xb[u]);
+    }
+    gsum[tid] = make_double2(hs, hc);
+    __syncthreads();
+    if (pw == 0 && r < nt && lane < 9) {
+        double ts = 0.0, tc = 0.0;
+#pragma unroll
+        for (int q = 0; q < WPT; ++q)
+#pragma unroll
+            for (int gq = 0; gq < kFinGroups; ++gq) {
+                const double2 e = gsum[(w + q) * 64 + lane * kFinGroups + gq];
+                comp_merge(ts, tc, e.x, e.y);
+            }
+        fs[r * 9 + lane] = ts + tc;
+    }
+}
+
 // Compensated slice sums, corrector, list updates, and (last workgroup) the
 // plan of the next block. Targets go in rounds of fin_per_round(split):
 // with few slices seg threads per target, four slices each (the slice sums
@@ -598,52 +626,17 @@ __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t s
         int id = 0, lev = 0;
         OldState old{};
         if (wide) {
-            // waves wpt * r .. wpt * r + wpt - 1: target k0 + r; lane (c, g) of
-            // the p-th of them sums slices g', g' + G, ... of component c, with
-            // g' = 7 p + g and G = 7 wpt
-            const int wpt = kFinThreads / 64 / per;
-            const int r = w / wpt, pw = w - r * wpt;
-            const int c = lane / kFinGroups, g = lane - kFinGroups * (lane / kFinGroups);
-            const int gg = pw * kFinGroups + g, G = kFinGroups * wpt;
-            const bool has = r < nt && c < 9;
-            const double *__restrict__ pc =
-                part + ((int64_t)(k0 + (has ? r : 0)) * 9 + (has ? c : 0)) * split + gg;
-            const int nq = has && gg < split ? (split - gg + G - 1) / G : 0;
-            constexpr int U = 16;
-            double xa[U], xb[U];
-            auto load = [&](double *x, int i0) {
-#pragma unroll
-                for (int u = 0; u < U; ++u) x[u] = i0 + u < nq ? pc[(int64_t)G * (i0 + u)] : 0.0;
+            auto particle = [&]() {
+                if (valid) {
+                    id = rank_to_particle(A, &rt, k0 + tid);
+                    old = load_old<false>(A.st, id);
+                }
             };
-            // the first slices, then the particle and its old state (list,
-            // then state: two dependent loads), all in flight together
-            const int nq_max = (split + G - 1) / G;
-            load(xa, 0);
-            if (valid) {
-                id = rank_to_particle(A, &rt, k0 + tid);
-                old = load_old<false>(A.st, id);
-            }
-            double hs = 0.0, hc = 0.0;
-            for (int i0 = 0; i0 < nq_max; i0 += 2 * U) {
-                if (i0 + U < nq_max) load(xb, i0 + U);
-#pragma unroll
-                for (int u = 0; u < U; ++u) two_sum_into(hs, hc, xa[u]);
-                if (i0 + U >= nq_max) break;
-                if (i0 + 2 * U < nq_max) load(xa, i0 + 2 * U);
-#pragma unroll
-                for (int u = 0; u < U; ++u) two_sum_into(hs, hc, xb[u]);
-            }
-            gsum[tid] = make_double2(hs, hc);
-            __syncthreads();
-            if (pw == 0 && r < nt && lane < 9) {
-                double ts = 0.0, tc = 0.0;
-                for (int q = 0; q < wpt; ++q)
-#pragma unroll
-                    for (int gq = 0; gq < kFinGroups; ++gq) {
-                        const double2 e = gsum[(w + q) * 64 + lane * kFinGroups + gq];
-                        comp_merge(ts, tc, e.x, e.y);
-                    }
-                fs[r * 9 + lane] = ts + tc;
+            switch (kFinThreads / 64 / per) {
+                case 1: fin_wide_sums<1>(part, k0, nt, split, gsum, fs, particle); break;
+                case 2: fin_wide_sums<2>(part, k0, nt, split, gsum, fs, particle); break;
+                case 4: fin_wide_sums<4>(part, k0, nt, split, gsum, fs, particle); break;
+                default: fin_wide_sums<8>(part, k0, nt, split, gsum, fs, particle); break;
             }
         } else {
             // thread tid = j * per + kl: slices 4j .. 4j + 3 of target k0 + kl

@@ -97,8 +97,11 @@ struct PredSrc {
 
 // Body of the target-parallel LDS-tiled evaluation for the workgroup that
 // owns target block ib (BLOCK * IPL targets) and source slice sl.
-// tile: BLOCK * Traits<ORDER>::NREC double2 of workgroup memory.
-template <int ORDER, int BLOCK, int IPL, bool SKIPSELF, class SRC>
+// tile: BLOCK * Traits<ORDER>::NREC double2 of workgroup memory. AHEAD
+// (order 2, one target per lane, kernels with registers to spare): the next
+// tile's source record is loaded while this tile's sums run, so that its
+// latency is hidden.
+template <int ORDER, int BLOCK, int IPL, bool SKIPSELF, bool AHEAD, class SRC>
 __device__ __forceinline__ void eval_tile_body(const SRC &S, int n, int n_act, double eps2,
                                                int slice_len, const OutPtrs &out,
                                                int64_t slice_stride, int ib, int sl,
@@ -130,32 +133,50 @@ __device__ __forceinline__ void eval_tile_body(const SRC &S, int n, int n_act, d
     const int jb = sl * slice_len;
     const int je = min(n, jb + slice_len);
 
+    // this thread's source record of the tile starting at jt (far massless
+    // padding past the slice end)
+    auto fetch = [&](int jt, double2 *rec) {
+        const int jj = jt + tid;
+        if (jj < je) {
+            double xs[3], vs[3], as[3], js[3];
+            S.template get<ORDER>(jj, xs, vs, as, js);
+            rec[0] = make_double2(xs[0], xs[1]);
+            rec[1] = make_double2(xs[2], S.mass(jj));
+            rec[2] = make_double2(vs[0], vs[1]);
+            if (ORDER == 1) {
+                rec[3] = make_double2(vs[2], 0.0);
+            } else {
+                rec[3] = make_double2(vs[2], as[0]);
+                rec[4] = make_double2(as[1], as[2]);
+            }
+            if (ORDER == 3) {
+                rec[5] = make_double2(js[0], js[1]);
+                rec[6] = make_double2(js[2], 0.0);
+            }
+        } else {
+            rec[0] = make_double2(kPadPos, kPadPos);
+            rec[1] = make_double2(kPadPos, 0.0);
+#pragma unroll
+            for (int q = 2; q < NREC; ++q) rec[q] = make_double2(0.0, 0.0);
+        }
+    };
+    constexpr bool kAhead = AHEAD && IPL == 1 && ORDER == 2;
+    double2 ahead[NREC];
+    if (kAhead && jb < je) fetch(jb, ahead);
+
     for (int jt = jb; jt < je; jt += BLOCK) {
         __syncthreads();  // previous tile fully consumed
         {
-            const int jj = jt + tid;
             double2 *rec = &tile[tid * NREC];
-            if (jj < je) {
-                double xs[3], vs[3], as[3], js[3];
-                S.template get<ORDER>(jj, xs, vs, as, js);
-                rec[0] = make_double2(xs[0], xs[1]);
-                rec[1] = make_double2(xs[2], S.mass(jj));
-                rec[2] = make_double2(vs[0], vs[1]);
-                if (ORDER == 1) {
-                    rec[3] = make_double2(vs[2], 0.0);
-                } else {
-                    rec[3] = make_double2(vs[2], as[0]);
-                    rec[4] = make_double2(as[1], as[2]);
-                }
-                if (ORDER == 3) {
-                    rec[5] = make_double2(js[0], js[1]);
-                    rec[6] = make_double2(js[2], 0.0);
-                }
-            } else {
-                rec[0] = make_double2(kPadPos, kPadPos);
-                rec[1] = make_double2(kPadPos, 0.0);
+            if constexpr (kAhead) {
 #pragma unroll
-                for (int q = 2; q < NREC; ++q) rec[q] = make_double2(0.0, 0.0);
+                for (int q = 0; q < NREC; ++q) rec[q] = ahead[q];
+                if (jt + BLOCK < je) fetch(jt + BLOCK, ahead);
+            } else {
+                double2 cur[NREC];
+                fetch(jt, cur);
+#pragma unroll
+                for (int q = 0; q < NREC; ++q) rec[q] = cur[q];
             }
         }
         __syncthreads();
@@ -385,8 +406,8 @@ __device__ __forceinline__ void eval_tile_body(const SrcPtrs &src,
                                                const OutPtrs &out, int64_t slice_stride, int ib,
                                                int sl) {
     __shared__ double2 tile[BLOCK * Traits<ORDER>::NREC];
-    eval_tile_body<ORDER, BLOCK, IPL, SKIPSELF>(PredSrc{src, active}, n, n_act, eps2, slice_len,
-                                                out, slice_stride, ib, sl, tile);
+    eval_tile_body<ORDER, BLOCK, IPL, SKIPSELF, false>(PredSrc{src, active}, n, n_act, eps2,
+                                                       slice_len, out, slice_stride, ib, sl, tile);
 }
 
 template <int TPW, bool SKIPSELF>

@@ -66,7 +66,6 @@ struct LoopDesc {
     int32_t slice_len;       // sources per slice
     int32_t L0;              // lowest active level
     int32_t lv_hi;           // highest occupied level
-    int32_t pred;            // 1: the block's sources are predicted into the predicted arrays
     int32_t cnt[kLevels];    // particles per level
     int32_t off[kLevels];    // first active rank of level L (L >= L0)
 };
