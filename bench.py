@@ -44,6 +44,10 @@ METRIC = "a/j/s pair interactions/s, % of vector FP peak, at stated rel. error v
 FLOPS_PER_INTERACTION = 78  # FMA 2, rsqrt 1, potential excluded
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBPS = 8000.0
+MIXED_N = 262144
+MIXED_ACCURACY_TARGETS = 256
+TRAFFIC_INTERVALS = 20  # sync intervals the committed HBM-traffic record covers
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eval_hbm_traffic.txt")
 CSRC = os.path.join(ROOT, "paper_1901_08532_amd", "csrc")
 # the evaluation kernels' sources: the traffic record is void once any changes
@@ -134,13 +138,15 @@ def main():
                          "(mass seed 10*seed+seed); two Plummer spheres of n/2 on a head-on "
                          "approach (seeds seed, 10*seed+seed); adjoint: gradient of a loss on "
                          "the final positions of 64 shared steps (one step = forward + backward)")
-    ap.add_argument("--accuracy-targets", type=int, default=64,
-                    help="sampled targets of the final state checked against the FP64 oracle")
+    ap.add_argument("--accuracy-targets", type=int, default=256,
+                    help="sampled targets of the last block checked against the FP64 oracle")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--host-loop", action="store_true",
                     help="one host round trip per block instead of the device-resident loop")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-vs-FP64 leg (power-law Plummer N = 262144, one sync interval each)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -230,15 +236,21 @@ def main():
     evals = [p for p in prof if p["order"] == 2]
     inst = {}
     bins = {}
+    empty_launches = 0
     for p in evals:
+        b = bins.setdefault(p["nact_log2"], {"launches": 0, "interactions": 0.0, "kernel_ms": 0.0})
+        for f in ("launches", "interactions", "kernel_ms"):
+            b[f] += p[f]
+        if p["nact_log2"] < 0:
+            # launches enqueued past the last due block: nothing evaluated
+            empty_launches += p["launches"]
+            continue
         key = (p["kind"], p["block"], p["ipl"])
         d = inst.setdefault(key, {"kind": p["kind"], "block": p["block"], "ipl": p["ipl"],
-                                  "launches": 0, "interactions": 0.0, "kernel_ms": 0.0})
-        b = bins.setdefault(p["nact_log2"], {"launches": 0, "interactions": 0.0, "kernel_ms": 0.0})
-        for tgt in (d, b):
-            tgt["launches"] += p["launches"]
-            tgt["interactions"] += p["interactions"]
-            tgt["kernel_ms"] += p["kernel_ms"]
+                                  "launches": 0, "interactions": 0.0, "kernel_ms": 0.0,
+                                  "bytes": 0.0})
+        for f in ("launches", "interactions", "kernel_ms", "bytes"):
+            d[f] += p[f]
     dom = max(inst.values(), key=lambda p: p["kernel_ms"])
     eval_ms = sum(p["kernel_ms"] for p in evals)
     by_active = []
@@ -262,13 +274,25 @@ def main():
         "traffic": traffic,
         "kernel": _kernel_name(dom, prec == h6.H6_MIXED),
         "launches": dom["launches"],
+        "empty_launches_excluded": empty_launches,
         "avg_launch_us": 1e3 * dom["kernel_ms"] / max(1, dom["launches"]),
         "flops_per_launch": FLOPS_PER_INTERACTION * dom["interactions"] / max(1, dom["launches"]),
+        "algorithmic_bytes_per_launch": dom["bytes"] / max(1, dom["launches"]),
+        "traffic_window": "per dispatch over %d timed sync intervals" % TRAFFIC_INTERVALS,
     }
     xfl = _executed_flops_per_interaction() if prec == h6.H6_FP64 else None
     if xfl is not None:
         roofline["executed_flops_per_interaction"] = xfl
         roofline["executed_tflops"] = achieved * xfl / FLOPS_PER_INTERACTION
+
+    # accuracy of the timed kernel itself: the last block of the run (at a
+    # sync time, every particle active) left its a, j, s in the state and
+    # its predicted sources in the work array; the oracle evaluates sampled
+    # targets from those predicted arrays
+    rng = np.random.Generator(np.random.PCG64(7))
+    acc = _loop_accuracy(sysg, m, eps, args.accuracy_targets, rng)
+    _log("accuracy of the loop's last block: a %.2e j %.2e s %.2e" % (
+        acc["max_rel_err_a"], acc["max_rel_err_j"], acc["max_rel_err_s"]))
 
     # timings of single passes on the final, synchronised state, HIP events
     # on the library's stream (torch's current one), mean of 10: (i) the
@@ -303,24 +327,10 @@ def main():
     }
     _log("eval+reduce of all %d: %.1f us; full step %.1f us" % (n, t_eval, t_step))
 
-    # accuracy vs the FP64 oracle on sampled targets of the final, synchronised state
     import oracle
 
-    rng = np.random.Generator(np.random.PCG64(7))
-    idx = np.sort(rng.choice(n, min(n, args.accuracy_targets), replace=False))
-    F = torch.empty((9, n), dtype=torch.float64, device="cuda")
     P = sysg.S[0:9].contiguous()
-    act = torch.from_numpy(idx.astype(np.int32)).cuda()
-    sysg.ctx.h6_evaluate(P, sysg.m, act, len(idx), prec, F)
-    torch.cuda.synchronize()
     xs, vs, as_ = (P[3 * k:3 * k + 3].T.cpu().numpy().copy() for k in range(3))
-    want = oracle.forces(xs, vs, m, eps * eps, a=as_, idx=idx, order=2)[:3]
-    acc = {}
-    for k, name in enumerate("ajs"):
-        got = F[3 * k:3 * k + 3, :len(idx)].T.cpu().numpy()
-        err = np.linalg.norm(got - want[k], axis=1) / np.linalg.norm(want[k], axis=1)
-        acc["max_rel_err_" + name] = float(err.max())
-    acc["sample_targets"] = len(idx)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -343,6 +353,16 @@ def main():
                       "of the final synchronised state (%.1f s)" % (n_i, n, tc),
         }
         _log("cpu baseline: %.3e interactions/s on %d threads" % (cpu["value"], cpu["cores"]))
+
+    # the three kernels of every block, timed over the first sync interval
+    # again (untimed: events on every dispatch cost wall time)
+    sysg.S.copy_(S0)
+    sysg.T.copy_(T0)
+    step_roofs = _loop_breakdown(sysg, sync_ticks, eta, lev_min, lev_max, prec)
+
+    mixed = None
+    if not args.no_mixed:
+        mixed = _mixed_vs_fp64(args, h6, ics, oracle)
 
     out = {
         "metric": METRIC,
@@ -376,12 +396,133 @@ def main():
         "energy_rel_err_max": drift,
         "accuracy": acc,
         "roofline": roofline,
+        "step_rooflines": step_roofs,
+        "mixed_vs_fp64": mixed,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
 
+def _loop_accuracy(sysg, m, eps, n_targets, rng):
+    """Largest per-particle relative error of the a, j, s that the device
+    loop's last block (a sync time: every particle active) left in the
+    state, against the FP64 oracle evaluated from the same block's
+    predicted arrays, on n_targets sampled particles."""
+    import numpy as np
+
+    import oracle
+
+    n = sysg.n
+    idx = np.sort(rng.choice(n, min(n, n_targets), replace=False))
+    P = sysg.P.cpu().numpy()
+    xp, vp, ap = P[0:3].T.copy(), P[3:6].T.copy(), P[6:9].T.copy()
+    want = oracle.forces(xp, vp, m, eps * eps, a=ap, idx=idx, order=2)[:3]
+    acc = {}
+    for k, name in enumerate("ajs"):
+        got = sysg.field(name)[idx]
+        err = np.linalg.norm(got - want[k], axis=1) / np.linalg.norm(want[k], axis=1)
+        acc["max_rel_err_" + name] = float(err.max())
+    acc["sample_targets"] = len(idx)
+    acc["source"] = "a, j, s of the timed run's last block (all particles active) as the loop left them"
+    return acc
+
+
+def _loop_breakdown(sysg, sync_ticks, eta, lev_min, lev_max, prec):
+    """One sync interval with the predictor, evaluation and finishing
+    kernels of every block event-timed (profile level 2): launches, time,
+    algorithmic bytes (each datum moved once, from the block's active count
+    and slice count) and the resulting fraction of the 8 TB/s HBM bound
+    per kernel. The events add about 3 us to each dispatch's measured time,
+    which dominates the smallest blocks' kernels."""
+    from paper_1901_08532_amd import h6
+
+    sysg.ctx.h6_profile_enable(2)
+    rc, stats = sysg.run_blocks(sync_ticks, eta, lev_min, lev_max, prec, check=False)
+    recs = sysg.ctx.h6_profile_read()
+    sysg.ctx.h6_profile_enable(False)
+    if rc != h6.H6_OK:
+        raise h6.H6Error(rc, "h6_run_blocks (breakdown)")
+    names = {2: "k_bl_eval", 3: "k_bl_predict", 4: "k_bl_finish"}
+    agg = {k: {"launches": 0, "kernel_ms": 0.0, "bytes": 0.0} for k in names}
+    for r in recs:
+        if r["kind"] in names and r["nact_log2"] >= 0:
+            a = agg[r["kind"]]
+            a["launches"] += r["launches"]
+            a["kernel_ms"] += r["kernel_ms"]
+            a["bytes"] += r["bytes"]
+    total_ms = sum(a["kernel_ms"] for a in agg.values())
+    out = {"interval_blocks": stats.blocks, "window": "the first sync interval, events on every dispatch"}
+    for k, name in names.items():
+        a = agg[k]
+        secs = a["kernel_ms"] * 1e-3
+        gbs = a["bytes"] / secs / 1e9 if secs > 0 else 0.0
+        out[name] = {
+            "bound": "hbm" if k != 2 else "alu",
+            "launches": a["launches"],
+            "avg_us": 1e3 * a["kernel_ms"] / max(1, a["launches"]),
+            "share_of_loop_gpu_time": a["kernel_ms"] / total_ms if total_ms > 0 else None,
+            "algorithmic_bytes_per_launch": a["bytes"] / max(1, a["launches"]),
+            "achieved_GBps": gbs,
+            "peak_GBps": HBM_PEAK_GBPS,
+            "frac_of_hbm": gbs / HBM_PEAK_GBPS,
+        }
+    return out
+
+
+def _mixed_vs_fp64(args, h6, ics, oracle):
+    """The power-law-mass workload (Plummer N = 262144, seeds 3 and 33,
+    eps 1e-4): one sync interval from the same start-up state in FP64 and
+    in the mixed form; rate of each, the mixed form's speedup, each run's
+    a, j, s error (the evaluation kernel's own output at the interval's
+    last block, against the FP64 oracle on sampled targets) and energy
+    drift over the interval."""
+    import numpy as np
+    import torch
+
+    n, eps, eta, lev_min, lev_max = MIXED_N, 1e-4, 0.4, 4, 30
+    sync = 1 << (h6.TICK_BITS - lev_min)
+    x, v, _ = ics.plummer(n, 3)
+    m = ics.salpeter_masses(n, 33)
+    base = h6.System(x, v, m, eps)
+    base.startup(eta_s=0.1, lev_min=lev_min, lev_max=lev_max)
+    S0, T0 = base.S.clone(), base.T.clone()
+    e0 = sum(base.energy()[:2])
+    res = {"workload": "plummer_imf_n%d_eps1e-4_seed3_masses33_blocksteps_1/16tu" % n}
+    for tag, prec in (("fp64", h6.H6_FP64), ("mixed", h6.H6_MIXED)):
+        base.S.copy_(S0)
+        base.T.copy_(T0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = base.run_blocks(sync, eta, lev_min, lev_max, prec, check=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if rc != h6.H6_OK:
+            raise h6.H6Error(rc, "h6_run_blocks (%s)" % tag)
+        e1 = sum(base.energy()[:2])
+        rng = np.random.Generator(np.random.PCG64(333))
+        acc = _loop_accuracy(base, m, eps, MIXED_ACCURACY_TARGETS, rng)
+        rate = st.interactions / wall
+        res[tag] = {
+            "interactions_per_s": rate,
+            "pct_fp64_vector_peak": 100.0 * rate * FLOPS_PER_INTERACTION / (FP64_PEAK_TFLOPS * 1e12),
+            "pct_fp32_vector_peak": 100.0 * rate * FLOPS_PER_INTERACTION / (FP32_PEAK_TFLOPS * 1e12),
+            "blocks": st.blocks,
+            "wall_s": wall,
+            "max_rel_err_a": acc["max_rel_err_a"],
+            "max_rel_err_j": acc["max_rel_err_j"],
+            "max_rel_err_s": acc["max_rel_err_s"],
+            "energy_rel_err": abs(e1 - e0) / abs(e0),
+        }
+        _log("mixed_vs_fp64 %s: %.3e interactions/s, %d blocks, a/j/s err %.1e %.1e %.1e" % (
+            tag, rate, st.blocks, acc["max_rel_err_a"], acc["max_rel_err_j"], acc["max_rel_err_s"]))
+    res["speedup"] = res["mixed"]["interactions_per_s"] / res["fp64"]["interactions_per_s"]
+    res["energy_drift_ratio"] = res["mixed"]["energy_rel_err"] / max(res["fp64"]["energy_rel_err"], 1e-300)
+    res["sample_targets"] = MIXED_ACCURACY_TARGETS
+    return res
+
+
 VJP_COUNTER_FILE = os.path.join(ROOT, "profiles", "eval_vjp_valu_counters.md")
+VJP_FLOPS_PER_PAIR = 235  # algorithmic flops of one pair's order-2 VJP (FMA 2, rsqrt 1)
 ADJ_METRIC = "pair-sum passes x N^2 per second, forward sums and their vector-Jacobian products"
 
 
@@ -503,18 +644,23 @@ def run_adjoint(args):
     t_eval = timed(lambda: ctx.h6_evaluate(P, M0, None, n, h6.H6_FP64, F))
     t_vjp = timed(lambda: ctx.h6_evaluate_vjp(P, M0, CF, CP, gm))
     pairs = float(n) * n
+    achieved = VJP_FLOPS_PER_PAIR * pairs / t_vjp / 1e12
     fpp = _vjp_flops_per_pair()
-    achieved = fpp * pairs / t_vjp / 1e12 if fpp is not None else None
     roofline = {
         "bound": "alu",
         "achieved": achieved,
         "peak": FP64_PEAK_TFLOPS,
         "unit": "TFLOP/s",
-        "frac": achieved / FP64_PEAK_TFLOPS if achieved is not None else None,
+        "frac": achieved / FP64_PEAK_TFLOPS,
         "traffic": _vjp_traffic_per_launch(),  # of the k_eval_vjp dispatch alone
         "kernel": "k_eval_vjp<2, 128, 0> + slice reduction (one h6_evaluate_vjp call)",
-        "flops_per_pair": fpp,
-        "flops_convention": "executed FP64 flops per pair from the VALU counters (FMA 2, ADD/MUL/TRANS 1)",
+        "flops_per_pair": VJP_FLOPS_PER_PAIR,
+        "flops_convention": "algorithmic: the operations of the factored reverse sweep of one "
+                            "pair (forward recompute 44, six dot products and G, G_alpha per "
+                            "cotangent 2 x 43, mass weights 9, scalars 12, gradient sums 36, "
+                            "source-cotangent terms 42, target scalar sums 6); FMA 2, rsqrt 1",
+        "executed_flops_per_pair": fpp,
+        "executed_tflops": fpp * pairs / t_vjp / 1e12 if fpp is not None else None,
         "avg_call_us": 1e6 * t_vjp,
     }
 

@@ -449,6 +449,12 @@ typedef struct {
     double interactions; /* sum of n_act * n over the launches (kinds 3, 4:
                             those of the blocks they belong to) */
     double kernel_ms;    /* sum of the event-measured kernel durations */
+    double bytes;        /* sum of the launches' algorithmic HBM bytes, each
+                            datum moved once: order-2 evaluations 80 B per
+                            source + 76 B per target + 72 B per target and
+                            slice written; predictor 224 B per particle;
+                            finishing kernel 296 B + 72 B per slice per
+                            active particle (0 for the start-up passes) */
 } h6_eval_timing;
 
 int h6_profile_enable(h6_ctx ctx, int on);

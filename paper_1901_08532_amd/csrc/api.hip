@@ -138,6 +138,21 @@ namespace h6 {
 static int timing_key(h6_ctx ctx, int order, int kind, int block, int ipl, int precision,
                       int bin);
 
+// Algorithmic HBM bytes of the measured kernels (each datum moved once):
+// an order-2 evaluation reads the predicted x, v, a and the mass of every
+// source (80 B), the predicted state and list entry of every target (76 B)
+// and writes 9 doubles per target and slice; the predictor reads x, v, a,
+// j, s, c and t (152 B) and writes x, v, a (72 B) per particle; the
+// finishing kernel reads the slice sums (72 B per slice) and, per active
+// particle, its list entry and old x, v, a, j, s and step (132 B), and
+// writes x, v, a, j, s, c, t, step and a list entry (164 B).
+constexpr double kSliceBytes = 72.0;
+constexpr double kPredictBytes = 224.0;
+constexpr double kFinishStateBytes = 296.0;
+static double eval_bytes(double n_src, double n_act, int split) {
+    return 80.0 * n_src + n_act * (76.0 + kSliceBytes * (split > 1 ? split : 0));
+}
+
 hipError_t prof_events(h6_ctx ctx, hipEvent_t *e0, hipEvent_t *e1) {
     for (hipEvent_t *e : {e0, e1}) {
         if (!ctx->event_pool.empty()) {
@@ -165,7 +180,9 @@ hipError_t prof_end(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int order, const E
     int bin = 0;
     for (int64_t na = n_act; na > 1; na >>= 1) ++bin;
     const int key = timing_key(ctx, order, cfg.kind, cfg.block, cfg.ipl, precision, bin);
-    ctx->pending.push_back({e0, e1, key, interactions, -1, precision, 0});
+    const double n_src = n_act > 0 ? interactions / (double)n_act : 0.0;
+    const double bytes = order == 2 ? eval_bytes(n_src, (double)n_act, cfg.n_split) : 0.0;
+    ctx->pending.push_back({e0, e1, key, interactions, -1, precision, 0, bytes});
     return hipSuccess;
 }
 
@@ -174,7 +191,7 @@ hipError_t prof_end(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int order, const E
 // block sequence number) resolves it.
 hipError_t prof_push_seq(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int precision, int64_t seq,
                          int kind) {
-    ctx->pending.push_back({e0, e1, -1, 0.0, seq, precision, kind});
+    ctx->pending.push_back({e0, e1, -1, 0.0, seq, precision, kind, 0.0});
     return hipSuccess;
 }
 
@@ -186,7 +203,7 @@ static int timing_key(h6_ctx ctx, int order, int kind, int block, int ipl, int p
             t.precision == precision && t.nact_log2 == bin)
             return (int)q;
     }
-    h6_eval_timing t = {order, kind, block, ipl, precision, bin, 0, 0.0, 0.0};
+    h6_eval_timing t = {order, kind, block, ipl, precision, bin, 0, 0.0, 0.0, 0.0};
     ctx->timings.push_back(t);
     return (int)ctx->timings.size() - 1;
 }
@@ -198,25 +215,37 @@ hipError_t prof_resolve(h6_ctx ctx) {
         hipError_t r = hipEventElapsedTime(&ms, p.e0, p.e1);
         if (r != hipSuccess) return r;
         int key = p.key;
-        double inter = p.interactions;
+        double inter = p.interactions, bytes = p.bytes;
         if (key < 0) {
             if (log.empty()) {
-                log.resize((size_t)ctx->bl_log_mask + 1);
+                log.resize(2 * ((size_t)ctx->bl_log_mask + 1));
                 r = hipMemcpy(log.data(), ctx->bl_log, log.size() * sizeof(int32_t),
                               hipMemcpyDeviceToHost);
                 if (r != hipSuccess) return r;
             }
-            const int64_t na = log[(size_t)(p.seq & ctx->bl_log_mask)];
+            const size_t e = 2 * (size_t)(p.seq & ctx->bl_log_mask);
+            const int64_t na = log[e];
+            const int split = log[e + 1];
             int bin = -1;  // empty block (nothing evaluated)
             for (int64_t q = na; q >= 1; q >>= 1) ++bin;
             key = p.kind == 2 ? timing_key(ctx, 2, 2, 64, 2, p.precision, bin)
                               : timing_key(ctx, 2, p.kind, 0, 0, p.precision, bin);
-            inter = (double)na * (double)ctx->bl_n;
+            const double n = (double)ctx->bl_n;
+            inter = (double)na * n;
+            if (na == 0)
+                bytes = 0.0;
+            else if (p.kind == 2)
+                bytes = eval_bytes(n, (double)na, split);
+            else if (p.kind == 3)
+                bytes = kPredictBytes * n;
+            else
+                bytes = (double)na * (kFinishStateBytes + kSliceBytes * split);
         }
         h6_eval_timing &t = ctx->timings[key];
         t.launches += 1;
         t.interactions += inter;
         t.kernel_ms += ms;
+        t.bytes += bytes;
         ctx->event_pool.push_back(p.e0);
         ctx->event_pool.push_back(p.e1);
     }
@@ -865,8 +894,8 @@ int h6_profile_enable(h6_ctx ctx, int on) {
     H6_TRY(ctx, prof_resolve(ctx), "profile events");
     if (on && !ctx->bl_log) {
         const int cap = 1 << 20;
-        H6_TRY(ctx, hipMalloc(&ctx->bl_log, sizeof(int32_t) * cap), "block log");
-        H6_TRY(ctx, hipMemset(ctx->bl_log, 0, sizeof(int32_t) * cap), "block log");
+        H6_TRY(ctx, hipMalloc(&ctx->bl_log, 2 * sizeof(int32_t) * cap), "block log");
+        H6_TRY(ctx, hipMemset(ctx->bl_log, 0, 2 * sizeof(int32_t) * cap), "block log");
         ctx->bl_log_mask = cap - 1;
     }
     ctx->timings.clear();

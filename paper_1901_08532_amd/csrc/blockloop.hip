@@ -323,7 +323,11 @@ __device__ void plan_block(const LoopArgs &A, LoopDesc *d, const int *cnt, int64
     d->blocks = blocks;
     d->particle_steps = psteps;
     d->n_act = n_act;
-    if (A.nact_log) A.nact_log[seq_next & A.log_mask] = n_act;
+    if (A.nact_log) {
+        int32_t *e = A.nact_log + 2 * (seq_next & A.log_mask);
+        e[0] = n_act;
+        e[1] = done ? 0 : d->split;
+    }
 }
 
 // List slots handed out in a block: the sizes of the rebuilt lists of the
@@ -593,7 +597,10 @@ __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t s
         // nothing due before t_end: carry the final descriptor forward
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             *dn = *d;
-            if (A.nact_log) A.nact_log[(seq + 1) & A.log_mask] = 0;
+            if (A.nact_log) {
+                int32_t *e = A.nact_log + 2 * ((seq + 1) & A.log_mask);
+                e[0] = e[1] = 0;
+            }
         }
         return;
     }
@@ -813,7 +820,7 @@ __global__ void k_bl_setup_plan(LoopArgs A) {
         d->n_act = 0;
         d->done = 1;
         d->t_next = 0;
-        if (A.nact_log) A.nact_log[0] = 0;
+        if (A.nact_log) A.nact_log[0] = A.nact_log[1] = 0;
         return;
     }
     if (threadIdx.x == 0) scr->bad = 0u;

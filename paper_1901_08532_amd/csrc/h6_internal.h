@@ -103,7 +103,7 @@ struct LoopArgs {
     int eval_grid;
     unsigned pc_pairs;    // partial capacity / 9: bound on split * n_act
     int32_t *flags;
-    int32_t *nact_log;    // n_act by block sequence number (ring), or NULL
+    int32_t *nact_log;    // (n_act, split) by block sequence number (ring of pairs), or NULL
     int log_mask;
 };
 
@@ -141,7 +141,7 @@ struct h6_ctx_s {
     h6::LoopScratch *bl_scr = nullptr;   // device
     int32_t *bl_lists = nullptr;         // device level lists
     int64_t bl_lists_cap = 0;            // ints
-    int32_t *bl_log = nullptr;     // n_act per block sequence number (ring), profiling only
+    int32_t *bl_log = nullptr;     // (n_act, split) per block sequence number (ring), profiling only
     int bl_log_mask = 0;
     hipEvent_t bl_ev[2] = {nullptr, nullptr};
     int64_t bl_n = 0;              // particle count of the current loop (profiling)
@@ -153,6 +153,7 @@ struct h6_ctx_s {
         int64_t seq;         // block sequence number (device loop)
         int precision;
         int kind;            // device loop: 2 evaluation, 3 predictor, 4 finishing kernel
+        double bytes;        // algorithmic bytes (host-shaped evaluations)
     };
     bool prof = false;
     int prof_level = 0;  // 1: evaluation kernels; 2: also the device loop's other kernels

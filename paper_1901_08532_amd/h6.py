@@ -55,7 +55,8 @@ class h6_run_stats(C.Structure):
 class h6_eval_timing(C.Structure):
     _fields_ = [("order", C.c_int), ("kind", C.c_int), ("block", C.c_int), ("ipl", C.c_int),
                 ("precision", C.c_int), ("nact_log2", C.c_int),
-                ("launches", C.c_int64), ("interactions", C.c_double), ("kernel_ms", C.c_double)]
+                ("launches", C.c_int64), ("interactions", C.c_double), ("kernel_ms", C.c_double),
+                ("bytes", C.c_double)]
 
 
 class H6Error(RuntimeError):

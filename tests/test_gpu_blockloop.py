@@ -117,6 +117,36 @@ def test_device_loop_profile_records():
     assert all(r["kernel_ms"] > 0 for r in real)
 
 
+def test_device_loop_profile_records_of_all_three_kernels():
+    # level 2: the predictor and finishing kernels of every block too, with
+    # the algorithmic bytes of each record from the block's (n_act, split)
+    n = 8192
+    x, v, m = ics.plummer(n, 12)
+    s = h6.System(x, v, m, EPS)
+    s.startup(eta_s=0.1, lev_min=4, lev_max=30)
+    s.ctx.h6_profile_enable(2)
+    rc, st = s.run_blocks(SYNC, 0.4, 4, 30)
+    recs = s.ctx.h6_profile_read()
+    s.ctx.h6_profile_enable(False)
+    assert rc == h6.H6_OK
+    by_kind = {}
+    for r in recs:
+        if r["nact_log2"] >= 0 and r["kind"] in (2, 3, 4):
+            d = by_kind.setdefault(r["kind"], [0, 0.0, 0.0])
+            d[0] += r["launches"]
+            d[1] += r["interactions"]
+            d[2] += r["bytes"]
+    for kind in (2, 3, 4):
+        assert by_kind[kind][0] == st.blocks, kind
+        assert by_kind[kind][1] == pytest.approx(st.interactions), kind
+    assert by_kind[3][2] == 224.0 * n * st.blocks  # every block predicts all n
+    # finishing kernel: 296 B per active particle plus 72 B per slice
+    assert by_kind[4][2] >= (296.0 + 72.0) * st.particle_steps
+    assert by_kind[4][2] <= (296.0 + 72.0 * 4096) * st.particle_steps
+    # evaluation: at least every source and target once per block
+    assert by_kind[2][2] >= 80.0 * n * st.blocks + 76.0 * st.particle_steps
+
+
 def _host_vs_device(s_dev, s_host, t_end, lev_min, lev_max):
     rd, sd = s_dev.run_blocks(t_end, 0.4, lev_min, lev_max)
     rh, sh = s_host.run_blocks(t_end, 0.4, lev_min, lev_max, host_loop=True)
