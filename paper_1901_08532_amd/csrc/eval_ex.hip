@@ -14,9 +14,11 @@
 //   TwoSum (Knuth): s = fl(a + b) and the exact error of that addition;
 //   Fast2Sum (Dekker): the same when |a| >= |b|, in three operations;
 //   TwoProd: p = fl(a b) and its exact error fma(a, b, -p).
-// Addition is the accurate form (TwoSum on both the high and the low parts,
-// then two renormalisations), so that the differences of nearby positions
-// keep their full double-single precision. Multiplication adds the two cross
+// The differences of nearby coordinates use the accurate addition (TwoSum
+// on both the high and the low parts, then two renormalisations), so that
+// they keep their full double-single precision; the other sums (of
+// products, and the accumulations) the sloppy one, whose operand-relative
+// error is that of the terms it adds. Multiplication adds the two cross
 // products into the error of the high product. The reciprocal square root
 // starts from the hardware single-precision estimate and takes one
 // third-order Newton step in double-single. Only float operations are used
@@ -74,7 +76,27 @@ __device__ __forceinline__ fpair ds_add(fpair x, fpair y) {
     return fast_two_sum(s.h, s.l);
 }
 
+// The sum without the error-free addition of the low parts (the "sloppy"
+// form, 11 operations against 20): exact sum of the high parts, the low
+// parts and its error added in float, renormalised. Its error is about
+// 2u^2 (|x| + |y|), u = 2^-24: relative to the result when x and y have
+// the same sign, to the operands' size when they cancel. The pair terms
+// carry operand-relative errors of that size anyway (every product, sum of
+// products and accumulation is rounded relative to its operands), so it is
+// used for those; the differences of nearby coordinates, whose relative
+// precision the pair terms need, keep the accurate form.
+__device__ __forceinline__ fpair ds_add_sloppy(fpair x, fpair y) {
+#pragma clang fp contract(off)
+    fpair s = two_sum(x.h, y.h);
+    s.l += x.l + y.l;
+    return fast_two_sum(s.h, s.l);
+}
+
 __device__ __forceinline__ fpair ds_neg(fpair x) { return {-x.h, -x.l}; }
+
+__device__ __forceinline__ fpair ds_sub_sloppy(fpair x, fpair y) {
+    return ds_add_sloppy(x, ds_neg(y));
+}
 
 __device__ __forceinline__ fpair ds_sub(fpair x, fpair y) { return ds_add(x, ds_neg(y)); }
 
@@ -90,6 +112,23 @@ __device__ __forceinline__ fpair ds_mul(fpair x, fpair y) {
     fpair p = two_prod(x.h, y.h);
     p.l = fmaf(x.h, y.l, fmaf(x.l, y.h, p.l));
     return fast_two_sum(p.h, p.l);
+}
+
+// Products that only feed a sloppy sum skip the final renormalisation: the
+// sum adds the low parts in float and renormalises itself, so a low part a
+// few ulp of the high one larger costs nothing measurable.
+__device__ __forceinline__ fpair ds_mul_raw(fpair x, fpair y) {
+#pragma clang fp contract(off)
+    fpair p = two_prod(x.h, y.h);
+    p.l = fmaf(x.h, y.l, fmaf(x.l, y.h, p.l));
+    return p;
+}
+
+__device__ __forceinline__ fpair ds_sqr_raw(fpair x) {
+#pragma clang fp contract(off)
+    fpair p = two_prod(x.h, x.h);
+    p.l = fmaf(x.h + x.h, x.l, p.l);
+    return p;
 }
 
 __device__ __forceinline__ fpair ds_mul_f(fpair x, float b) {
@@ -132,7 +171,8 @@ __device__ __forceinline__ fpair ds_rsqrt(fpair r2) {
 }
 
 __device__ __forceinline__ fpair ds_dot3(const fpair *p, const fpair *q) {
-    return ds_add(ds_add(ds_mul(p[0], q[0]), ds_mul(p[1], q[1])), ds_mul(p[2], q[2]));
+    return ds_add_sloppy(ds_add_sloppy(ds_mul_raw(p[0], q[0]), ds_mul_raw(p[1], q[1])),
+                         ds_mul_raw(p[2], q[2]));
 }
 
 // Pair terms of order 2 in double-single, added to acc[0..8]: with
@@ -148,18 +188,19 @@ __device__ __forceinline__ void pair_ex(const fpair *r, const fpair *v, const fp
     const fpair a3 = ds_mul_f(alpha, 3.0f);
     fpair w[3], u[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) w[c] = ds_sub(v[c], ds_mul(a3, r[c]));
-    const fpair vvra = ds_add(ds_dot3(v, v), ds_dot3(r, a));
-    const fpair beta = ds_add(ds_sqr(alpha), ds_mul(vvra, rinv2));
+    for (int c = 0; c < 3; ++c) w[c] = ds_sub_sloppy(v[c], ds_mul_raw(a3, r[c]));
+    const fpair vvra = ds_add_sloppy(ds_dot3(v, v), ds_dot3(r, a));
+    const fpair beta = ds_add_sloppy(ds_sqr_raw(alpha), ds_mul_raw(vvra, rinv2));
     const fpair b3 = ds_mul_f(beta, 3.0f);
     const fpair a6 = ds_scale2(a3, 2.0f);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) u[c] = ds_sub(ds_sub(a[c], ds_mul(a6, w[c])), ds_mul(b3, r[c]));
+    for (int c = 0; c < 3; ++c)
+        u[c] = ds_sub_sloppy(ds_sub_sloppy(a[c], ds_mul_raw(a6, w[c])), ds_mul_raw(b3, r[c]));
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        acc[c] = ds_add(acc[c], ds_mul(mr3, r[c]));
-        acc[3 + c] = ds_add(acc[3 + c], ds_mul(mr3, w[c]));
-        acc[6 + c] = ds_add(acc[6 + c], ds_mul(mr3, u[c]));
+        acc[c] = ds_add_sloppy(acc[c], ds_mul_raw(mr3, r[c]));
+        acc[3 + c] = ds_add_sloppy(acc[3 + c], ds_mul_raw(mr3, w[c]));
+        acc[6 + c] = ds_add_sloppy(acc[6 + c], ds_mul_raw(mr3, u[c]));
     }
 }
 
@@ -231,7 +272,9 @@ __global__ __launch_bounds__(BLOCK) void k_eval_ex(SrcPtrs src, const int32_t *_
                 v[c] = ds_sub(f[3 + c], vi[c]);
                 a[c] = ds_sub(f[6 + c], ai[c]);
             }
-            fpair r2 = ds_add(ds_add(ds_add(eps2, ds_sqr(r[0])), ds_sqr(r[1])), ds_sqr(r[2]));
+            fpair r2 = ds_add_sloppy(
+                ds_add_sloppy(ds_add_sloppy(eps2, ds_sqr_raw(r[0])), ds_sqr_raw(r[1])),
+                ds_sqr_raw(r[2]));
             fpair mj = f[9];
             if (SKIPSELF && (jt + q) == p) {  // r, v, a are zero: mask the 1/0
                 r2 = {1.0f, 0.0f};

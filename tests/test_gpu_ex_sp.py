@@ -7,7 +7,9 @@ Stated bounds, per target particle (vector norms), from the arithmetic:
   split, whose error (u |x|) grows to u |x| / |r| in a difference r; with
   |x| / |r| up to ~100 for close pairs and the cancellation of the sums,
   the bound is 2e-12 (a), 4e-12 (j), 1e-11 (s), about 500-3000 u. The
-  largest errors measured on these inputs are 1.9e-13, 3.7e-13 and 1.3e-12.
+  largest errors measured on these inputs are 1.9e-13, 2.3e-13 and 9.4e-13
+  (the sums of products and the accumulations in the "sloppy" double-single
+  addition, whose operand-relative error is that of the terms it adds).
 * SP: u = 2^-24 = 6.0e-8; same reasoning, bound 1e-4 (a), 2e-4 (j), 5e-4
   (s), against 7.9e-6, 1.1e-5, 4.1e-5 measured.
 The typical (median) EX error is that of SP times about 2^-24: the test
