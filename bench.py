@@ -242,7 +242,8 @@ def main():
         for f in ("launches", "interactions", "kernel_ms"):
             b[f] += p[f]
         if p["nact_log2"] < 0:
-            # launches enqueued past the last due block: nothing evaluated
+            # launches enqueued past the last due block (bin -1) and those of
+            # prediction slots (bin -2): nothing evaluated
             empty_launches += p["launches"]
             continue
         key = (p["kind"], p["block"], p["ipl"])
@@ -285,12 +286,13 @@ def main():
         roofline["executed_flops_per_interaction"] = xfl
         roofline["executed_tflops"] = achieved * xfl / FLOPS_PER_INTERACTION
 
-    # accuracy of the timed kernel itself: the last block of the run (at a
-    # sync time, every particle active) left its a, j, s in the state and
-    # its predicted sources in the work array; the oracle evaluates sampled
-    # targets from those predicted arrays
+    # accuracy of the timed kernel itself: one more sync interval of the same
+    # loop (untimed), whose last block (every particle active) leaves its
+    # a, j, s in the state; the oracle evaluates sampled targets from that
+    # block's predicted arrays
     rng = np.random.Generator(np.random.PCG64(7))
-    acc = _loop_accuracy(sysg, m, eps, args.accuracy_targets, rng)
+    acc = _loop_accuracy(sysg, (args.steps + 1) * sync_ticks, eta, lev_min, lev_max, prec, m, eps,
+                         args.accuracy_targets, rng)
     _log("accuracy of the loop's last block: a %.2e j %.2e s %.2e" % (
         acc["max_rel_err_a"], acc["max_rel_err_j"], acc["max_rel_err_s"]))
 
@@ -403,18 +405,30 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def _loop_accuracy(sysg, m, eps, n_targets, rng):
+def _loop_accuracy(sysg, t_end, eta, lev_min, lev_max, prec, m, eps, n_targets, rng):
     """Largest per-particle relative error of the a, j, s that the device
-    loop's last block (a sync time: every particle active) left in the
-    state, against the FP64 oracle evaluated from the same block's
-    predicted arrays, on n_targets sampled particles."""
+    loop's block at t_end (a sync time: every particle active) leaves in
+    the state, against the FP64 oracle evaluated from that block's predicted
+    arrays, on n_targets sampled particles. The loop runs to one tick before
+    t_end, the library's predictor takes every particle to t_end (the code
+    of the loop's own prediction slot), then the loop runs the block."""
     import numpy as np
+    import torch
 
     import oracle
+    from paper_1901_08532_amd import h6
 
+    rc, _ = sysg.run_blocks(t_end - 1, eta, lev_min, lev_max, prec, check=False)
+    if rc != h6.H6_OK:
+        raise h6.H6Error(rc, "h6_run_blocks (accuracy interval)")
+    Pt = torch.zeros_like(sysg.P)
+    sysg.ctx.h6_predict(sysg.S, sysg.m, sysg.T, t_end, Pt)
+    rc, st = sysg.run_blocks(t_end, eta, lev_min, lev_max, prec, check=False)
+    if rc != h6.H6_OK or st.particle_steps != sysg.n:
+        raise h6.H6Error(rc, "h6_run_blocks (accuracy block)")
     n = sysg.n
     idx = np.sort(rng.choice(n, min(n, n_targets), replace=False))
-    P = sysg.P.cpu().numpy()
+    P = Pt.cpu().numpy()
     xp, vp, ap = P[0:3].T.copy(), P[3:6].T.copy(), P[6:9].T.copy()
     want = oracle.forces(xp, vp, m, eps * eps, a=ap, idx=idx, order=2)[:3]
     acc = {}
@@ -423,13 +437,15 @@ def _loop_accuracy(sysg, m, eps, n_targets, rng):
         err = np.linalg.norm(got - want[k], axis=1) / np.linalg.norm(want[k], axis=1)
         acc["max_rel_err_" + name] = float(err.max())
     acc["sample_targets"] = len(idx)
-    acc["source"] = "a, j, s of the timed run's last block (all particles active) as the loop left them"
+    acc["source"] = ("a, j, s that the loop's evaluation kernel left at a sync block (all "
+                     "particles active), one untimed interval after the timed ones")
     return acc
 
 
 def _loop_breakdown(sysg, sync_ticks, eta, lev_min, lev_max, prec):
-    """One sync interval with the predictor, evaluation and finishing
-    kernels of every block event-timed (profile level 2): launches, time,
+    """One sync interval with the evaluation and finishing kernels of every
+    block event-timed (profile level 2; the finishing kernels of the
+    prediction slots apart, their evaluations are empty): launches, time,
     algorithmic bytes (each datum moved once, from the block's active count
     and slice count) and the resulting fraction of the 8 TB/s HBM bound
     per kernel. The events add about 3 us to each dispatch's measured time,
@@ -442,14 +458,18 @@ def _loop_breakdown(sysg, sync_ticks, eta, lev_min, lev_max, prec):
     sysg.ctx.h6_profile_enable(False)
     if rc != h6.H6_OK:
         raise h6.H6Error(rc, "h6_run_blocks (breakdown)")
-    names = {2: "k_bl_eval", 3: "k_bl_predict", 4: "k_bl_finish"}
+    names = {2: "k_bl_eval", 4: "k_bl_finish", -4: "k_bl_finish (prediction slots)"}
     agg = {k: {"launches": 0, "kernel_ms": 0.0, "bytes": 0.0} for k in names}
     for r in recs:
-        if r["kind"] in names and r["nact_log2"] >= 0:
-            a = agg[r["kind"]]
-            a["launches"] += r["launches"]
-            a["kernel_ms"] += r["kernel_ms"]
-            a["bytes"] += r["bytes"]
+        if r["kind"] not in (2, 4) or r["nact_log2"] == -1:
+            continue
+        key = r["kind"] if r["nact_log2"] >= 0 else -r["kind"]
+        if key not in agg:
+            continue  # empty evaluations of prediction slots
+        a = agg[key]
+        a["launches"] += r["launches"]
+        a["kernel_ms"] += r["kernel_ms"]
+        a["bytes"] += r["bytes"]
     total_ms = sum(a["kernel_ms"] for a in agg.values())
     out = {"interval_blocks": stats.blocks, "window": "the first sync interval, events on every dispatch"}
     for k, name in names.items():
@@ -500,7 +520,8 @@ def _mixed_vs_fp64(args, h6, ics, oracle):
             raise h6.H6Error(rc, "h6_run_blocks (%s)" % tag)
         e1 = sum(base.energy()[:2])
         rng = np.random.Generator(np.random.PCG64(333))
-        acc = _loop_accuracy(base, m, eps, MIXED_ACCURACY_TARGETS, rng)
+        acc = _loop_accuracy(base, 2 * sync, eta, lev_min, lev_max, prec, m, eps,
+                             MIXED_ACCURACY_TARGETS, rng)
         rate = st.interactions / wall
         res[tag] = {
             "interactions_per_s": rate,

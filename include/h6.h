@@ -270,10 +270,15 @@ int h6_block_step(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred,
  * no later than any particle's time plus step -- which holds after
  * h6_initial_steps and after any block steps with the same levels; a state
  * that is not on the grid is run with the host loop instead (same results).
- * The lists take 8 * (lev_max - lev_min + 1) * n bytes of device memory,
+ * The lists take 8 * (lev_max - lev_min + 1) * n bytes of device memory
+ * (and 2 n bytes of per-particle levels),
  * allocated by the first call that needs them and kept by the context
  * (H6_ENOMEM if that fails). pred and f are used as work arrays; the
- * device loop writes no forces to f.
+ * device loop writes no forces to f. On return pred holds, from the device
+ * loop, every particle predicted to the last block's time plus the step of
+ * its highest occupied level (the loop predicts each next block while
+ * finishing the one before); from the host loop, the last block's own
+ * predicted arrays.
  *
  * Both loops take the same block sequence; the evaluation shapes (and
  * hence last-bit rounding) may differ. Errors: as h6_block_step; H6_ESTATE
@@ -428,8 +433,8 @@ int h6_energy_vjp(h6_ctx ctx, const h6_state *st, int64_t n, const double *cot_e
  * evaluation kernel the context launches (on its stream), and the event
  * durations are accumulated per kernel instantiation and per power-of-two
  * bin of the active-set size. on = 2 also times the device-resident loop's
- * predictor and finishing kernels of every block (records of kind 3 and 4,
- * binned by the block's active count like its evaluation). on = 0 turns the
+ * finishing kernel of every block (records of kind 4, binned by the block's
+ * active count like its evaluation). on = 0 turns the
  * hook off. Enabling clears the records. h6_profile_read (synchronizes)
  * copies up to max records to out and sets *count.
  * Errors: H6_EINVAL (on outside 0..2), H6_EHIP.
@@ -438,23 +443,28 @@ typedef struct {
     int order;      /* 2: per-step a/j/s; 1, 3: start-up passes */
     int kind;       /* 0: LDS-tiled kernel; 1: source-parallel small-set kernel;
                        2: evaluation kernel of the device-resident loop (its
-                       shape is chosen per block on the device); 3, 4: the
-                       loop's predictor and finishing kernels (on = 2) */
+                       shape is chosen per block on the device); 4: the
+                       loop's finishing kernel (on = 2) */
     int block, ipl; /* launch shape of the instantiation (kind 2: 64, 2;
-                       kinds 3, 4: 0, 0) */
+                       kind 4: 0, 0) */
     int precision;  /* H6_FP64, H6_MIXED, H6_EX or H6_SP */
     int nact_log2;  /* bin: floor(log2(n_act)) of the launches in this record;
-                       -1: device-loop launches of blocks with nothing due */
+                       -1: device-loop launches of blocks with nothing due;
+                       -2: prediction slots of the device loop (the
+                       finishing kernel predicts every particle to the
+                       planned block time; the evaluation does nothing) */
     int64_t launches;
-    double interactions; /* sum of n_act * n over the launches (kinds 3, 4:
-                            those of the blocks they belong to) */
+    double interactions; /* sum of n_act * n over the launches (kind 4:
+                            those of the blocks they belong to; 0 for
+                            prediction slots) */
     double kernel_ms;    /* sum of the event-measured kernel durations */
     double bytes;        /* sum of the launches' algorithmic HBM bytes, each
                             datum moved once: order-2 evaluations 80 B per
                             source + 76 B per target + 72 B per target and
-                            slice written; predictor 224 B per particle;
-                            finishing kernel 296 B + 72 B per slice per
-                            active particle (0 for the start-up passes) */
+                            slice written; finishing kernel 368 B + 72 B
+                            per slice per active particle and 224 B per
+                            inactive one (prediction slots: 224 B per
+                            particle); 0 for the start-up passes */
 } h6_eval_timing;
 
 int h6_profile_enable(h6_ctx ctx, int on);

@@ -141,14 +141,15 @@ static int timing_key(h6_ctx ctx, int order, int kind, int block, int ipl, int p
 // Algorithmic HBM bytes of the measured kernels (each datum moved once):
 // an order-2 evaluation reads the predicted x, v, a and the mass of every
 // source (80 B), the predicted state and list entry of every target (76 B)
-// and writes 9 doubles per target and slice; the predictor reads x, v, a,
-// j, s, c and t (152 B) and writes x, v, a (72 B) per particle; the
-// finishing kernel reads the slice sums (72 B per slice) and, per active
-// particle, its list entry and old x, v, a, j, s and step (132 B), and
-// writes x, v, a, j, s, c, t, step and a list entry (164 B).
+// and writes 9 doubles per target and slice; predicting a particle reads
+// x, v, a, j, s, c and t (152 B) and writes x, v, a (72 B); the finishing
+// kernel reads the slice sums (72 B per slice) and, per active particle, its
+// list entry and old x, v, a, j, s and step (132 B), and writes x, v, a, j,
+// s, c, t, step, a list entry (164 B) and the predicted x, v, a (72 B), and
+// predicts every inactive particle (224 B each).
 constexpr double kSliceBytes = 72.0;
 constexpr double kPredictBytes = 224.0;
-constexpr double kFinishStateBytes = 296.0;
+constexpr double kFinishStateBytes = 368.0;
 static double eval_bytes(double n_src, double n_act, int split) {
     return 80.0 * n_src + n_act * (76.0 + kSliceBytes * (split > 1 ? split : 0));
 }
@@ -186,9 +187,9 @@ hipError_t prof_end(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int order, const E
     return hipSuccess;
 }
 
-// Device-loop launch (kind 2 evaluation, 3 predictor, 4 finishing kernel):
-// its active count is known only on the device; the block log (n_act per
-// block sequence number) resolves it.
+// Device-loop launch (kind 2 evaluation, 4 finishing kernel): its active
+// count is known only on the device; the block log ((n_act, split) per slot
+// sequence number, split -1 for a prediction slot) resolves it.
 hipError_t prof_push_seq(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int precision, int64_t seq,
                          int kind) {
     ctx->pending.push_back({e0, e1, -1, 0.0, seq, precision, kind, 0.0});
@@ -226,20 +227,24 @@ hipError_t prof_resolve(h6_ctx ctx) {
             const size_t e = 2 * (size_t)(p.seq & ctx->bl_log_mask);
             const int64_t na = log[e];
             const int split = log[e + 1];
+            const bool pslot = split < 0;  // prediction slot: no evaluation
             int bin = -1;  // empty block (nothing evaluated)
             for (int64_t q = na; q >= 1; q >>= 1) ++bin;
+            if (pslot) bin = -2;
             key = p.kind == 2 ? timing_key(ctx, 2, 2, 64, 2, p.precision, bin)
                               : timing_key(ctx, 2, p.kind, 0, 0, p.precision, bin);
             const double n = (double)ctx->bl_n;
             inter = (double)na * n;
-            if (na == 0)
+            if (pslot) inter = 0.0;
+            if (na == 0 || (pslot && p.kind == 2))
                 bytes = 0.0;
+            else if (pslot)
+                bytes = kPredictBytes * n;
             else if (p.kind == 2)
                 bytes = eval_bytes(n, (double)na, split);
-            else if (p.kind == 3)
-                bytes = kPredictBytes * n;
             else
-                bytes = (double)na * (kFinishStateBytes + kSliceBytes * split);
+                bytes = (double)na * (kFinishStateBytes + kSliceBytes * split) +
+                        kPredictBytes * (n - (double)na);
         }
         h6_eval_timing &t = ctx->timings[key];
         t.launches += 1;
@@ -611,6 +616,7 @@ static int run_blocks_device(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred 
     A.lev_lo = prm->lev_min;
     A.nl = nl;
     A.lists = ctx->bl_lists;
+    A.lvl = (uint8_t *)(ctx->bl_lists + 2 * (int64_t)nl * n);
     A.desc = ctx->bl_desc;
     A.scr = ctx->bl_scr;
     A.partial = ctx->partial;

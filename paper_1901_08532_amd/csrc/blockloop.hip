@@ -17,17 +17,21 @@
 // List order is not significant: a target's sums do not depend on which
 // targets share its group.
 //
-// Per block, three kernels in stream order:
-//   k_bl_predict  every particle predicted to t_next into the predicted
-//                 arrays (measured on this GPU: even for one or two active
-//                 particles at N = 65536 this pass plus an evaluation that
-//                 reads predicted sources is faster than predicting each
-//                 source in every evaluation wave that reads it).
+// Per block, two kernels in stream order:
 //   k_bl_eval     fixed grid; each workgroup takes (target group, source
 //                 slice) units and writes slice sums, reading sources and
 //                 targets from the predicted arrays.
-//   k_bl_finish   compensated slice sums, corrector in place, list updates;
-//                 the last workgroup plans the next block.
+//   k_bl_finish   compensated slice sums, corrector in place, list updates,
+//                 and the prediction of every particle to the next block's
+//                 likely time (the highest occupied level is always active,
+//                 so unless a correction changes that level the next block
+//                 comes one of its steps later); the last workgroup plans
+//                 the next block. A wrong guess costs one prediction slot
+//                 (the same two kernels: an empty evaluation, then a full
+//                 prediction to the planned time). Measured on this GPU,
+//                 predicting each source in every evaluation wave that
+//                 reads it is slower than this, even for one or two active
+//                 particles at N = 65536.
 // Only the finishing workgroups (at most kFinGrid, fewer for small sets)
 // synchronise through device-scope atomics: on this GPU such fences and
 // atomics serialise across the device, so per-block atomics stay few.
@@ -107,7 +111,7 @@ struct RankTable {
 struct DescHead {
     int64_t t_next;
     unsigned long long sel;
-    int n_act, split, slice_len, groups, kind, L0, lv_hi;
+    int n_act, split, slice_len, groups, kind, L0, lv_hi, pred_ok;
     int my_off, my_cnt;
 };
 __device__ __forceinline__ DescHead load_head(const LoopDesc *__restrict__ d) {
@@ -121,6 +125,7 @@ __device__ __forceinline__ DescHead load_head(const LoopDesc *__restrict__ d) {
     h.kind = d->kind;
     h.L0 = d->L0;
     h.lv_hi = d->lv_hi;
+    h.pred_ok = d->pred_ok;
     const int t = threadIdx.x < kLevels ? threadIdx.x : 0;
     h.my_off = d->off[t];
     h.my_cnt = d->cnt[t];
@@ -274,10 +279,13 @@ __device__ __forceinline__ int fin_workers(int n_act, int split) {
 // LDS; d->cnt is written by the caller), with blocks / particle_steps the
 // totals so far: next block time, active levels and count, rank offsets,
 // evaluation shape; n_act = 0 and done = 1 once t_next would pass t_end.
+// t_spec: the time every particle was predicted to (-1: none), which makes
+// the plan's pred_ok.
 // One wave (all 64 lanes call it), lane L for level L: a wave minimum gives
 // t_next, a ballot the occupied levels, a suffix scan the rank offsets.
 __device__ void plan_block(const LoopArgs &A, LoopDesc *d, const int *cnt, int64_t t_cur,
-                           uint64_t sel, int64_t blocks, int64_t psteps, int64_t seq_next) {
+                           uint64_t sel, int64_t blocks, int64_t psteps, int64_t seq_next,
+                           int64_t t_spec) {
     static_assert(kLevels <= 64, "one lane per level");
     const int L = threadIdx.x & 63;
     const bool listed = L >= A.lev_lo && L < A.lev_lo + A.nl;
@@ -323,10 +331,14 @@ __device__ void plan_block(const LoopArgs &A, LoopDesc *d, const int *cnt, int64
     d->blocks = blocks;
     d->particle_steps = psteps;
     d->n_act = n_act;
+    // the finishing kernel predicted every particle to t_spec: right unless
+    // the highest occupied level changed; else the next slot predicts
+    const bool pred_ok = !done && tn == t_spec;
+    d->pred_ok = pred_ok ? 1 : 0;
     if (A.nact_log) {
         int32_t *e = A.nact_log + 2 * (seq_next & A.log_mask);
         e[0] = n_act;
-        e[1] = done ? 0 : d->split;
+        e[1] = done ? 0 : (pred_ok ? d->split : -1);
     }
 }
 
@@ -344,7 +356,7 @@ struct Tally {
 // update of the block: one thread per level gathers, one thread plans from
 // LDS. solo: the tallies are this workgroup's (LDS), else the device's.
 __device__ void plan_next(const LoopArgs &A, const LoopDesc *__restrict__ cur, const int *cur_cnt,
-                          const Tally *solo, LoopDesc *dn, int64_t seq) {
+                          const Tally *solo, LoopDesc *dn, int64_t seq, int64_t t_spec) {
     __shared__ int s_cnt[kLevels];
     LoopScratch *scr = A.scr;
     const int L0 = cur->L0;
@@ -376,16 +388,8 @@ __device__ void plan_next(const LoopArgs &A, const LoopDesc *__restrict__ cur, c
         const int lo = L0 > A.lev_lo ? L0 : A.lev_lo;
         const uint64_t flip = ((1ull << (A.lev_lo + A.nl)) - 1ull) & ~((1ull << lo) - 1ull);
         plan_block(A, dn, s_cnt, cur->t_next, cur->sel ^ flip, cur->blocks, cur->particle_steps,
-                   seq + 1);
+                   seq + 1, t_spec);
     }
-}
-
-__global__ __launch_bounds__(256) void k_bl_predict(LoopArgs A, int64_t seq) {
-    const LoopDesc *__restrict__ d = A.desc + (seq & 1);
-    if (d->n_act == 0) return;
-    const int64_t tn = d->t_next;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += gridDim.x * blockDim.x)
-        predict_one(A.st, i, (double)(tn - A.st.t[i]) * kTick, A.pred);
 }
 
 template <bool MIXED, bool SKIPSELF>
@@ -394,7 +398,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const LoopDesc *__restrict__ d = A.desc + (seq & 1);
     const DescHead h = load_head(d);
     const int n_act = h.n_act;
-    if (n_act == 0) return;
+    if (n_act == 0 || !h.pred_ok) return;  // nothing due, or a prediction slot
     const int split = h.split, slice_len = h.slice_len, groups = h.groups;
     const int kind = h.kind;
     // slice sums: with few slices (the finishing kernel gives each target a
@@ -579,51 +583,19 @@ __device__ __forceinline__ void fin_wide_sums(const double *__restrict__ part, i
     }
 }
 
-// Compensated slice sums, corrector, list updates, and (last workgroup) the
-// plan of the next block. Targets go in rounds of fin_per_round(split):
-// with few slices seg threads per target, four slices each (the slice sums
-// stored target-minor, so the loads are coalesced), merged in order; with more,
-// one wave per target whose lanes are (component, group) -- 9 x 7 -- each
-// summing every 7th slice of its component (stored slice-minor, loads of a
-// component coalesced), the 7 group sums then merged in order through LDS.
-// The corrected particles' list slots are reserved once per level for up
-// to kStash particles.
-__global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t seq) {
-    const LoopDesc *__restrict__ d = A.desc + (seq & 1);
-    LoopDesc *dn = A.desc + ((seq + 1) & 1);
-    const DescHead h = load_head(d);
-    const int n_act = h.n_act;
-    if (n_act == 0) {
-        // nothing due before t_end: carry the final descriptor forward
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            *dn = *d;
-            if (A.nact_log) {
-                int32_t *e = A.nact_log + 2 * ((seq + 1) & A.log_mask);
-                e[0] = e[1] = 0;
-            }
-        }
-        return;
-    }
-    const int split = h.split;
-    const bool wide = split > kFinSplitNarrow;
-    const int per = fin_per_round(split);
-    const int workers = fin_workers(n_act, split);
-    if ((int)blockIdx.x >= workers) return;
+// The targets of one finishing workgroup (rounds of per targets): slice
+// sums, corrector, prediction of the corrected particle to t_spec, list
+// insertion; then the plan of the next block by the last workgroup.
+__device__ __forceinline__ void finish_targets(const LoopArgs &A, const DescHead &h,
+                                               const LoopDesc *__restrict__ d, LoopDesc *dn,
+                                               int64_t seq, int per, int workers, bool solo,
+                                               bool wide, int64_t t_spec, const RankTable *rtp,
+                                               const int *cur_cnt, Tally *tally, double *fs,
+                                               double2 *gsum, int32_t *st_id, uint8_t *st_lev) {
+    const RankTable &rt = *rtp;
+    const int n_act = h.n_act, split = h.split;
     const int64_t tn = h.t_next;
-    const bool solo = workers == 1;  // no other workgroup: tallies in LDS, no device atomics
-    __shared__ double fs[kFinThreads * 9];
-    __shared__ double2 gsum[kFinThreads];  // wide: group sums, [wave][component * 7 + group]
-    __shared__ int32_t st_id[kStash];
-    __shared__ uint8_t st_lev[kStash];
-    __shared__ RankTable rt;
-    __shared__ int cur_cnt[kLevels];
-    __shared__ Tally tally;
-    if (threadIdx.x < kLevels) {
-        cur_cnt[threadIdx.x] = h.my_cnt;
-        tally.reb[threadIdx.x] = 0u;
-    }
-    if (threadIdx.x == 0) tally.app = 0u;
-    rank_table_from(&rt, h);  // ends with a barrier
+    const double d_spec = (double)(t_spec - tn) * kTick;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const double *__restrict__ part = A.partial;
     int nst = 0;
@@ -707,24 +679,135 @@ __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t s
             }
             A.st.t[id] = tn;
             A.st.dt[id] = (int64_t)1 << (kTickBits - lev);
+            A.lvl[((seq + 1) & 1) * (int64_t)A.n + id] = (uint8_t)lev;
+            // its prediction to the guessed next block time, from registers
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double xp, vp, ap;
+                predict_comp(x1[c], v1[c], f[c], f[3 + c], f[6 + c], c1[c], d_spec, xp, vp, ap);
+                A.pred.x[c][id] = xp;
+                A.pred.v[c][id] = vp;
+                A.pred.a[c][id] = ap;
+            }
             st_id[nst + tid] = id;
             st_lev[nst + tid] = (uint8_t)lev;
         }
         nst += nt;
         const bool last = k0 + workers * per >= n_act;
         if (last || nst + per > kStash) {
-            list_insert_stash(A, &rt, cur_cnt, solo ? &tally : nullptr, st_id, st_lev, nst);
+            list_insert_stash(A, &rt, cur_cnt, solo ? tally : nullptr, st_id, st_lev, nst);
             nst = 0;
         } else {
             __syncthreads();  // fs and gsum reusable
         }
     }
     if (solo) {
-        plan_next(A, d, cur_cnt, &tally, dn, seq);
+        plan_next(A, d, cur_cnt, tally, dn, seq, t_spec);
         return;
     }
     if (!arrive_last(&A.scr->done_fin, (unsigned)workers)) return;
-    plan_next(A, d, cur_cnt, nullptr, dn, seq);
+    plan_next(A, d, cur_cnt, nullptr, dn, seq, t_spec);
+}
+
+// Prediction to t_to of the particles not due in the block (all of them in
+// a prediction slot), in index order (coalesced; the level lists are in no
+// useful order) by workgroups wg0 .. gridDim.x - 1. A particle is due iff its
+// level at the block's start (level bytes, buffer seq & 1) is L0 or more;
+// the finishing workgroups predict those themselves and write their new
+// levels, so each entry of the next level buffer has one writer, and no
+// thread here reads a state that is being corrected.
+__device__ __forceinline__ void predict_rest(const LoopArgs &A, int L0, int64_t seq, int64_t t_to,
+                                             int wg0, bool all) {
+    const uint8_t *__restrict__ cur = A.lvl + (seq & 1) * (int64_t)A.n;
+    uint8_t *__restrict__ nxt = A.lvl + ((seq + 1) & 1) * (int64_t)A.n;
+    const int stride = ((int)gridDim.x - wg0) * (int)blockDim.x;
+    for (int i = ((int)blockIdx.x - wg0) * (int)blockDim.x + (int)threadIdx.x; i < A.n; i += stride) {
+        const int lev = cur[i];
+        if (!all && lev >= L0) continue;
+        nxt[i] = (uint8_t)lev;
+        predict_one(A.st, i, (double)(t_to - A.st.t[i]) * kTick, A.pred);
+    }
+}
+
+// Compensated slice sums, corrector, list updates, and (last workgroup) the
+// plan of the next block. Targets go in rounds of fin_per_round(split):
+// with few slices seg threads per target, four slices each (the slice sums
+// stored target-minor, so the loads are coalesced), merged in order; with more,
+// one wave per target whose lanes are (component, group) -- 9 x 7 -- each
+// summing every 7th slice of its component (stored slice-minor, loads of a
+// component coalesced), the 7 group sums then merged in order through LDS.
+// The corrected particles' list slots are reserved once per level for up
+// to kStash particles. Every corrected particle is then predicted, from
+// registers, to the guessed next block time t_spec (the step of the highest
+// occupied level after t_next); the workgroups without targets (all of them,
+// after their targets, when every one has some) predict the particles not
+// due to t_spec as well, in index order, so no separate prediction pass runs
+// before the next evaluation. The plan records whether the guess held; if
+// not, the next slot is a prediction slot: its evaluation does nothing and
+// its finishing kernel predicts every particle to the planned time and
+// hands the same plan on.
+__global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t seq) {
+    const LoopDesc *__restrict__ d = A.desc + (seq & 1);
+    LoopDesc *dn = A.desc + ((seq + 1) & 1);
+    const DescHead h = load_head(d);
+    const int n_act = h.n_act;
+    if (n_act == 0) {
+        // nothing due before t_end: carry the final descriptor forward
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            *dn = *d;
+            if (A.nact_log) {
+                int32_t *e = A.nact_log + 2 * ((seq + 1) & A.log_mask);
+                e[0] = e[1] = 0;
+            }
+        }
+        return;
+    }
+    const int64_t tn = h.t_next;
+    if (!h.pred_ok) {
+        // prediction slot: every particle to the planned block's time (the
+        // last finishing kernel's guess was wrong); the block runs next slot
+        predict_rest(A, h.L0, seq, tn, 0, true);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            *dn = *d;
+            dn->pred_ok = 1;
+            if (A.nact_log) {
+                int32_t *e = A.nact_log + 2 * ((seq + 1) & A.log_mask);
+                e[0] = n_act;
+                e[1] = h.split;
+            }
+        }
+        return;
+    }
+    // the guess of the next block time: the highest occupied level (always
+    // active) is due again after its step, unless a correction changes it
+    const int64_t t_spec = tn + ((int64_t)1 << (kTickBits - h.lv_hi));
+    const int split = h.split;
+    const bool wide = split > kFinSplitNarrow;
+    const int per = fin_per_round(split);
+    const int workers = fin_workers(n_act, split);
+    if ((int)blockIdx.x >= workers) {
+        // no targets: the particles not due, to t_spec
+        predict_rest(A, h.L0, seq, t_spec, workers, false);
+        return;
+    }
+    const bool solo = workers == 1;  // no other workgroup: tallies in LDS, no device atomics
+    __shared__ double fs[kFinThreads * 9];
+    __shared__ double2 gsum[kFinThreads];  // wide: group sums, [wave][component * 7 + group]
+    __shared__ int32_t st_id[kStash];
+    __shared__ uint8_t st_lev[kStash];
+    __shared__ RankTable rt;
+    __shared__ int cur_cnt[kLevels];
+    __shared__ Tally tally;
+    if (threadIdx.x < kLevels) {
+        cur_cnt[threadIdx.x] = h.my_cnt;
+        tally.reb[threadIdx.x] = 0u;
+    }
+    if (threadIdx.x == 0) tally.app = 0u;
+    rank_table_from(&rt, h);  // ends with a barrier
+    finish_targets(A, h, d, dn, seq, per, workers, solo, wide, t_spec, &rt, cur_cnt, &tally, fs,
+                   gsum, st_id, st_lev);
+    // every workgroup has targets: the particles not due afterwards
+    if (workers == (int)gridDim.x) predict_rest(A, h.L0, seq, t_spec, 0, false);
 }
 
 // ---------------------------------------------------------------- set-up
@@ -792,7 +875,10 @@ __global__ __launch_bounds__(kScanThreads) void k_bl_setup_scan(LoopArgs A) {
     for (int L = threadIdx.x; L < kLevels; L += blockDim.x)
         if (lcount[L] > 0) lbase[L] = add_agent(&A.scr->reb[L][0], lcount[L]);
     __syncthreads();
-    if (good) level_list(A, 0, lev)[lbase[lev] + rank] = i;
+    if (good) {
+        level_list(A, 0, lev)[lbase[lev] + rank] = i;
+        A.lvl[i] = (uint8_t)lev;  // level buffer 0: slot 0 reads it
+    }
 }
 
 // Level counts from the fill, then the plan of block 0 into desc[0]; a
@@ -824,14 +910,14 @@ __global__ void k_bl_setup_plan(LoopArgs A) {
         return;
     }
     if (threadIdx.x == 0) scr->bad = 0u;
-    if (threadIdx.x < 64) plan_block(A, d, s_cnt, (int64_t)tmax, 0ull, 0, 0, 0);
+    if (threadIdx.x < 64) plan_block(A, d, s_cnt, (int64_t)tmax, 0ull, 0, 0, 0, -1);
 }
 
 }  // namespace
 
 int bl_eval_grid(h6_ctx ctx) { return ctx->n_cu * 8; }  // one round of resident tile workgroups
 
-int64_t bl_list_ints(int64_t n, int nl) { return 2 * (int64_t)nl * n; }
+int64_t bl_list_ints(int64_t n, int nl) { return 2 * (int64_t)nl * n + (2 * n + 3) / 4; }
 
 hipError_t bl_setup(h6_ctx ctx, const LoopArgs &A) {
     hipLaunchKernelGGL(k_bl_setup_init, dim3(1), dim3(64), 0, ctx->stream, A);
@@ -855,13 +941,8 @@ hipError_t bl_enqueue_block(h6_ctx ctx, const LoopArgs &A, int precision, int64_
         return pe != hipSuccess ? pe : prof_push_seq(ctx, e0, e1, precision, seq, kind);
     };
     hipEvent_t ev0, ev1;
-    hipError_t pe = events(&ev0, &ev1, all);
+    hipError_t pe = events(&ev0, &ev1, ctx->prof);
     if (pe != hipSuccess) return pe;
-    const int pgrid = ctx->n_cu > 1 ? ctx->n_cu / 2 : 1;
-    hipExtLaunchKernelGGL(k_bl_predict, dim3(pgrid), dim3(256), 0, ctx->stream, ev0, ev1, 0u, A,
-                          seq);
-    if ((pe = push(ev0, ev1, all, 3)) != hipSuccess) return pe;
-    if ((pe = events(&ev0, &ev1, ctx->prof)) != hipSuccess) return pe;
     const bool skip = self_pair_masked(A.eps2, precision);
     const bool mixed = precision == H6_MIXED;
 #define H6_BL_EVAL(M, S)                                                                         \

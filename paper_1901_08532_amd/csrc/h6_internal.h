@@ -66,6 +66,8 @@ struct LoopDesc {
     int32_t slice_len;       // sources per slice
     int32_t L0;              // lowest active level
     int32_t lv_hi;           // highest occupied level
+    int32_t pred_ok;         // 1: the predicted arrays hold every particle at t_next; 0: this
+                             // slot only predicts them, and the block runs in the next slot
     int32_t cnt[kLevels];    // particles per level
     int32_t off[kLevels];    // first active rank of level L (L >= L0)
 };
@@ -93,6 +95,8 @@ struct LoopArgs {
     int n;
     int lev_lo, nl;       // list levels lev_lo .. lev_lo + nl - 1
     int32_t *lists;       // [2][nl][n]
+    uint8_t *lvl;         // [2][n]: every particle's level at the start of slot seq, in
+                          // buffer seq & 1 (after the lists, in their allocation)
     LoopDesc *desc;       // [2]
     LoopScratch *scr;
     double *partial;      // [split][9][n_act]
@@ -103,7 +107,8 @@ struct LoopArgs {
     int eval_grid;
     unsigned pc_pairs;    // partial capacity / 9: bound on split * n_act
     int32_t *flags;
-    int32_t *nact_log;    // (n_act, split) by block sequence number (ring of pairs), or NULL
+    int32_t *nact_log;    // (n_act, split) by block sequence number (ring of pairs; split -1:
+                          // a prediction slot), or NULL
     int log_mask;
 };
 
@@ -231,7 +236,7 @@ hipError_t prof_resolve(h6_ctx ctx);  // stream must be idle
 
 // Device-resident block loop (blockloop.hip).
 int bl_eval_grid(h6_ctx ctx);
-int64_t bl_list_ints(int64_t n, int nl);  // list storage for n particles on nl levels
+int64_t bl_list_ints(int64_t n, int nl);  // list and level-byte storage, n particles, nl levels
 hipError_t bl_setup(h6_ctx ctx, const LoopArgs &A);  // lists and the plan of block 0
 hipError_t bl_enqueue_block(h6_ctx ctx, const LoopArgs &A, int precision, int64_t seq);
 int energy_blocks_for(int64_t n);

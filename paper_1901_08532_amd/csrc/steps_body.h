@@ -38,22 +38,27 @@ __device__ __forceinline__ double norm3(double a, double b, double c) {
 }
 
 // ---------------------------------------------------------------- predictor
-// Taylor prediction of particle i over interval d: x to 5th order, v to
+// Taylor prediction of one component over interval d: x to 5th order, v to
 // 4th, a to 3rd, Horner form.
+__device__ __forceinline__ void predict_comp(double x, double v, double a, double j, double s,
+                                             double cr, double d, double &xo, double &vo,
+                                             double &ao) {
+    // a_p = a + d (j + d/2 (s + d/3 c))
+    ao = fma(d, fma(d * 0.5, fma(d * (1.0 / 3.0), cr, s), j), a);
+    // v_p = v + d (a + d/2 (j + d/3 (s + d/4 c)))
+    vo = fma(d, fma(d * 0.5, fma(d * (1.0 / 3.0), fma(d * 0.25, cr, s), j), a), v);
+    // x_p = x + d (v + d/2 (a + d/3 (j + d/4 (s + d/5 c))))
+    xo = fma(d, fma(d * 0.5, fma(d * (1.0 / 3.0), fma(d * 0.25, fma(d * 0.2, cr, s), j), a), v),
+             x);
+}
+
+// Taylor prediction of particle i over interval d.
 __device__ __forceinline__ void predict_vals(const h6_state &st, int i, double d, double *xo,
                                              double *vo, double *ao) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const double x = st.x[c][i], v = st.v[c][i], a = st.a[c][i];
-        const double j = st.j[c][i], s = st.s[c][i], cr = st.c[c][i];
-        // a_p = a + d (j + d/2 (s + d/3 c))
-        ao[c] = fma(d, fma(d * 0.5, fma(d * (1.0 / 3.0), cr, s), j), a);
-        // v_p = v + d (a + d/2 (j + d/3 (s + d/4 c)))
-        vo[c] = fma(d, fma(d * 0.5, fma(d * (1.0 / 3.0), fma(d * 0.25, cr, s), j), a), v);
-        // x_p = x + d (v + d/2 (a + d/3 (j + d/4 (s + d/5 c))))
-        xo[c] = fma(
-            d, fma(d * 0.5, fma(d * (1.0 / 3.0), fma(d * 0.25, fma(d * 0.2, cr, s), j), a), v), x);
-    }
+    for (int c = 0; c < 3; ++c)
+        predict_comp(st.x[c][i], st.v[c][i], st.a[c][i], st.j[c][i], st.s[c][i], st.c[c][i], d,
+                     xo[c], vo[c], ao[c]);
 }
 
 __device__ __forceinline__ void predict_one(const h6_state &st, int i, double d,

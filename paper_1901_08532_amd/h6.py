@@ -374,7 +374,7 @@ class Context:
 
     def h6_profile_enable(self, on=True):
         """on: False/0 off, True/1 evaluation kernels, 2 also the device
-        loop's predictor and finishing kernels."""
+        loop's finishing kernels."""
         level = int(on) if not isinstance(on, bool) else (1 if on else 0)
         self._check(lib().h6_profile_enable(self._h, level), "h6_profile_enable")
 

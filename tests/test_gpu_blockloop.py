@@ -22,6 +22,24 @@ EPS = 1e-4
 SYNC = 1 << (TB - 4)
 
 
+def _predicted(s, t_tick):
+    """The host-sequenced predictor's arrays: every particle of s to t_tick."""
+    P = torch.zeros_like(s.P)
+    s.ctx.h6_predict(s.S, s.m, s.T, t_tick, P)
+    torch.cuda.synchronize()
+    return P
+
+
+def _assert_speculative_prediction(s, t_block, lv_hi_dt):
+    # after a block at t_block, the finishing kernel left every particle
+    # predicted to t_block plus the step of the block's highest occupied
+    # level (the next block's time unless a correction changed that level):
+    # bit for bit the predictor's result on the stored state
+    t_spec = int(t_block) + int(lv_hi_dt)
+    want = _predicted(s, t_spec)
+    assert torch.equal(s.P, want)
+
+
 def _from_oracle(st):
     sysg = h6.System(st.x, st.v, st.m, math.sqrt(st.eps2))
     for k, name in enumerate(("x", "v", "a", "j", "s", "c")):
@@ -117,9 +135,10 @@ def test_device_loop_profile_records():
     assert all(r["kernel_ms"] > 0 for r in real)
 
 
-def test_device_loop_profile_records_of_all_three_kernels():
-    # level 2: the predictor and finishing kernels of every block too, with
-    # the algorithmic bytes of each record from the block's (n_act, split)
+def test_device_loop_profile_records_of_both_kernels():
+    # level 2: the finishing kernel of every slot too, with the algorithmic
+    # bytes of each record from the slot's (n_act, split); prediction slots
+    # (bin -2) apart
     n = 8192
     x, v, m = ics.plummer(n, 12)
     s = h6.System(x, v, m, EPS)
@@ -129,20 +148,35 @@ def test_device_loop_profile_records_of_all_three_kernels():
     recs = s.ctx.h6_profile_read()
     s.ctx.h6_profile_enable(False)
     assert rc == h6.H6_OK
-    by_kind = {}
+    assert not [r for r in recs if r["kind"] == 3]  # no separate predictor
+    by_kind, slots = {}, {}
     for r in recs:
-        if r["nact_log2"] >= 0 and r["kind"] in (2, 3, 4):
+        if r["kind"] not in (2, 4):
+            continue
+        if r["nact_log2"] >= 0:
             d = by_kind.setdefault(r["kind"], [0, 0.0, 0.0])
             d[0] += r["launches"]
             d[1] += r["interactions"]
             d[2] += r["bytes"]
-    for kind in (2, 3, 4):
+        elif r["nact_log2"] == -2:
+            d = slots.setdefault(r["kind"], [0, 0.0, 0.0])
+            d[0] += r["launches"]
+            d[1] += r["interactions"]
+            d[2] += r["bytes"]
+    for kind in (2, 4):
         assert by_kind[kind][0] == st.blocks, kind
         assert by_kind[kind][1] == pytest.approx(st.interactions), kind
-    assert by_kind[3][2] == 224.0 * n * st.blocks  # every block predicts all n
-    # finishing kernel: 296 B per active particle plus 72 B per slice
-    assert by_kind[4][2] >= (296.0 + 72.0) * st.particle_steps
-    assert by_kind[4][2] <= (296.0 + 72.0 * 4096) * st.particle_steps
+    # the run's first slot predicts (its set-up makes no guess); each
+    # prediction slot: an empty evaluation, a prediction of all n
+    n_slots = slots[4][0]
+    assert 1 <= n_slots <= st.blocks and slots[2][0] == n_slots
+    assert slots[2][1] == slots[4][1] == 0.0 and slots[2][2] == 0.0
+    assert slots[4][2] == 224.0 * n * n_slots
+    # finishing kernel: 368 B per active particle plus 72 B per slice, and
+    # the prediction of every inactive particle (224 B)
+    inactive = 224.0 * (n * st.blocks - st.particle_steps)
+    assert by_kind[4][2] >= (368.0 + 72.0) * st.particle_steps + inactive
+    assert by_kind[4][2] <= (368.0 + 72.0 * 4096) * st.particle_steps + inactive
     # evaluation: at least every source and target once per block
     assert by_kind[2][2] >= 80.0 * n * st.blocks + 76.0 * st.particle_steps
 
@@ -232,6 +266,9 @@ def _one_block_against_host_loop_and_oracle(n, n_act, precision, seed=21, sample
         assert vec_rel_err(a.field(name), b.field(name)).max() < xv_tol, name
     for name in "ajs":  # two evaluations, each within the bound of the oracle's
         assert vec_rel_err(a.field(name), b.field(name)).max() < 2 * bound[name], name
+    # the device loop's prediction of the active (corrected) and inactive
+    # particles to the guessed next block time: level 5 was the highest
+    _assert_speculative_prediction(a, 1 << (TB - 5), 1 << (TB - 5))
     P = b.P.cpu().numpy()
     xp, vp, ap = P[0:3].T.copy(), P[3:6].T.copy(), P[6:9].T.copy()
     idx = act if n_act <= samples else np.sort(rng.choice(act, samples, replace=False))
@@ -277,10 +314,11 @@ def test_device_loop_two_clusters_full_activity_block(precision):
         s.S[k:k + 3] = torch.from_numpy(rng.normal(0.0, scale, (3, n))).to(DEV)
     s.T[0].zero_()
     s.T[1].fill_(1 << (TB - 4))
+    # the arrays the block evaluates from (its prediction slot's, bit for bit)
+    P = _predicted(s, 1 << (TB - 4)).cpu().numpy()
     rc, st = s.run_blocks(1 << (TB - 4), 0.4, 4, 30, precision, check=False)
     assert rc in (h6.H6_OK, h6.H6_EDTMIN)  # random derivatives may ask for tiny steps
     assert (st.blocks, st.particle_steps) == (1, n)
-    P = s.P.cpu().numpy()
     xp, vp, ap = P[0:3].T.copy(), P[3:6].T.copy(), P[6:9].T.copy()
     idx = np.sort(rng.choice(n, 256, replace=False))
     want = oracle.forces(xp, vp, m, EPS ** 2, a=ap, idx=idx, order=2)[:3]
@@ -310,22 +348,35 @@ def test_device_loop_full_size_sync_block_against_oracle(n, precision, imf):
     assert rc == h6.H6_OK and st.blocks > 100
     pre = {name: s.field(name) for name in ("x", "v", "a", "j", "s", "c")}
     t_pre = s.T[0].cpu().numpy()
+    dt_hi = int(s.T[1].min())  # step of the highest occupied level
     assert np.all(t_pre < SYNC)
+    # the arrays the sync block evaluates from: the run's first slot
+    # predicts every particle to SYNC with this same code
+    Pt = _predicted(s, SYNC)
     rc, st = s.run_blocks(SYNC, 0.4, 4, 30, precision)
     assert rc == h6.H6_OK and (st.blocks, st.particle_steps) == (1, n)
     assert bool((s.T[0] == SYNC).all())
-    P = s.P.cpu().numpy()
+    P = Pt.cpu().numpy()
     xp, vp, ap = P[0:3].T.copy(), P[3:6].T.copy(), P[6:9].T.copy()
-    # the loop's predictor (all particles, each over its own interval)
-    # against the oracle's on the pre-block state: the sum of the absolute
-    # Taylor terms bounds the rounding of both
-    delta = (SYNC - t_pre) * 2.0 ** -TB
-    want_p = oracle.predict(pre["x"], pre["v"], pre["a"], pre["j"], pre["s"], pre["c"], delta)
-    D = delta[:, None]
     order = ("x", "v", "a", "j", "s", "c")
-    for k, got_p in enumerate((xp, vp, ap)):
-        scale = sum(np.abs(pre[q]) * D ** (i - k) for i, q in enumerate(order) if i >= k)
-        assert np.all(np.abs(got_p - want_p[k]) <= 8e-16 * scale), k
+
+    def against_oracle_predict(st_in, delta, got):
+        # the predictor (every particle over its own interval) against the
+        # oracle's: the sum of the absolute Taylor terms bounds the rounding
+        # of both
+        want_p = oracle.predict(*(st_in[q] for q in order), delta)
+        D = delta[:, None]
+        for k in range(3):
+            scale = sum(np.abs(st_in[q]) * D ** (i - k) for i, q in enumerate(order) if i >= k)
+            assert np.all(np.abs(got[:, 3 * k:3 * k + 3] - want_p[k]) <= 8e-16 * scale), k
+
+    against_oracle_predict(pre, (SYNC - t_pre) * 2.0 ** -TB, P.T)
+    # the loop's own prediction after the block, of the corrected state to
+    # SYNC plus the step of the highest level: bit for bit the predictor's,
+    # and against the oracle's
+    _assert_speculative_prediction(s, SYNC, dt_hi)
+    post = {name: s.field(name) for name in order}
+    against_oracle_predict(post, np.full(n, dt_hi * 2.0 ** -TB), s.P.cpu().numpy().T)
     rng = np.random.Generator(np.random.PCG64(77))
     idx = np.sort(rng.choice(n, 256 if not imf else 1024, replace=False))
     want = oracle.forces(xp, vp, m, EPS ** 2, a=ap, idx=idx, order=2)[:3]
