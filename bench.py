@@ -47,7 +47,7 @@ FP32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBPS = 8000.0
 MIXED_N = 262144
 MIXED_ACCURACY_TARGETS = 256
-TRAFFIC_INTERVALS = 20  # sync intervals the committed HBM-traffic record covers
+TRAFFIC_INTERVALS = 16  # sync intervals the committed HBM-traffic record covers (the default --steps)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eval_hbm_traffic.txt")
 CSRC = os.path.join(ROOT, "paper_1901_08532_amd", "csrc")
 # the evaluation kernels' sources: the traffic record is void once any changes
@@ -356,7 +356,7 @@ def main():
         }
         _log("cpu baseline: %.3e interactions/s on %d threads" % (cpu["value"], cpu["cores"]))
 
-    # the three kernels of every block, timed over the first sync interval
+    # the two kernels of every block, timed over the first sync interval
     # again (untimed: events on every dispatch cost wall time)
     sysg.S.copy_(S0)
     sysg.T.copy_(T0)
@@ -486,6 +486,15 @@ def _loop_breakdown(sysg, sync_ticks, eta, lev_min, lev_max, prec):
             "peak_GBps": HBM_PEAK_GBPS,
             "frac_of_hbm": gbs / HBM_PEAK_GBPS,
         }
+    # measured HBM traffic of the finishing kernel (rocprofv3 counters over
+    # the default timed window, launches with nothing to do excluded: blocks
+    # and prediction slots alike) beside the algorithmic bytes of the same set
+    fin = [agg[4], agg[-4]]
+    n_fin = sum(a["launches"] for a in fin)
+    out["k_bl_finish"]["algorithmic_bytes_per_nonempty_launch"] = (
+        sum(a["bytes"] for a in fin) / max(1, n_fin))
+    out["k_bl_finish"]["traffic_per_nonempty_launch"] = _traffic_per_launch("bl_finish")
+    out["k_bl_finish"]["traffic_window"] = "per dispatch over %d timed sync intervals" % TRAFFIC_INTERVALS
     return out
 
 

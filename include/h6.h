@@ -470,6 +470,26 @@ typedef struct {
 int h6_profile_enable(h6_ctx ctx, int on);
 int h6_profile_read(h6_ctx ctx, h6_eval_timing *out, int max, int *count);
 
+/*
+ * The self pair (a particle as its own source) contributes nothing; the
+ * evaluation kernels either skip it by index or rely on its terms being
+ * m eps^-3 times an exact zero. They skip it when eps is below
+ * H6_SELF_MASK_EPS_F64 (FP64 pair arithmetic) or H6_SELF_MASK_EPS_F32 (the
+ * FP32-range arithmetics H6_MIXED, H6_EX, H6_SP), eps = 0 included; above,
+ * the unmasked self term stays an exact zero for masses below
+ * H6_SELF_MASK_MASS_F64 or H6_SELF_MASK_MASS_F32 (where m eps^-3 would
+ * overflow: larger masses need a larger eps, or units that make them
+ * smaller). h6_self_pair_masked returns 1 if the kernels of this precision
+ * skip the self pair for this eps, 0 if not; H6_EINVAL for a negative or
+ * non-finite eps or an unknown precision. A pure host function: no device
+ * work, no context.
+ */
+#define H6_SELF_MASK_EPS_F64 0x1p-300
+#define H6_SELF_MASK_EPS_F32 0x1p-30
+#define H6_SELF_MASK_MASS_F64 0x1p124 /* 2^1024 / 2^900 */
+#define H6_SELF_MASK_MASS_F32 0x1p38  /* 2^128 / 2^90 */
+int h6_self_pair_masked(double eps, int precision);
+
 /* Text of a return code; text of the context's last failure ("" if none). */
 const char *h6_strerror(int code);
 const char *h6_last_error(h6_ctx ctx);

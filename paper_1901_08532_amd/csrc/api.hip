@@ -262,6 +262,11 @@ hipError_t prof_resolve(h6_ctx ctx) {
 
 extern "C" {
 
+int h6_self_pair_masked(double eps, int precision) {
+    if (!std::isfinite(eps) || eps < 0.0 || !precision_ok(precision)) return H6_EINVAL;
+    return self_pair_masked(eps * eps, precision) ? 1 : 0;
+}
+
 const char *h6_strerror(int code) {
     switch (code) {
         case H6_OK: return "ok";

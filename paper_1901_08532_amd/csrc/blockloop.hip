@@ -56,7 +56,8 @@ constexpr int kTileBlock = 64;   // tile kinds: one-wave workgroups
 constexpr int kTileIpl = 2;      // targets per lane of tile kind 0
 constexpr int kTile1Max = 512;   // active sets up to this size: tile kind 2, one per lane
 constexpr int kFinThreads = 512;
-constexpr int kFinGrid = 128;    // finishing workgroups at most
+constexpr int kFinGrid = 128;    // finishing workgroups with targets at most
+constexpr int kFinLaunch = 2 * kFinGrid;  // finishing kernel grid: the rest only predict
 constexpr int kFinSplitNarrow = 64;  // slices up to this: threads over targets; more: a wave each
 constexpr int kFinGroups = 7;    // wave-per-target reduction: lanes per component (9 x 7 of 64)
 constexpr int kStash = 2048;     // corrected particles a finishing workgroup holds for insertion
@@ -956,7 +957,7 @@ hipError_t bl_enqueue_block(h6_ctx ctx, const LoopArgs &A, int precision, int64_
 #undef H6_BL_EVAL
     if ((pe = push(ev0, ev1, ctx->prof, 2)) != hipSuccess) return pe;
     if ((pe = events(&ev0, &ev1, all)) != hipSuccess) return pe;
-    hipExtLaunchKernelGGL(k_bl_finish, dim3(kFinGrid), dim3(kFinThreads), 0, ctx->stream, ev0,
+    hipExtLaunchKernelGGL(k_bl_finish, dim3(kFinLaunch), dim3(kFinThreads), 0, ctx->stream, ev0,
                           ev1, 0u, A, seq);
     if ((pe = push(ev0, ev1, all, 4)) != hipSuccess) return pe;
     return hipGetLastError();

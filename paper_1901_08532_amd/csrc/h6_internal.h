@@ -34,14 +34,21 @@ struct OutPtrs {
     int64_t kstride = 1;
 };
 
-// Whether the evaluation must mask the self pair. With a softening that is
-// nonzero in the arithmetic of the pair terms the self pair has r = v = a = 0
-// and contributes exactly zero; without it, r^2 = 0 and the term is 0 * inf.
-// The FP32-based arithmetics (mixed, EX, SP) see eps^2 rounded to FP32, where
-// a softening below ~1e-19 becomes zero or subnormal.
+// Whether the evaluation must mask the self pair (by index, which costs a
+// compare and two selects per pair). With a softening eps the self pair has
+// r = v = a = 0 and R^2 = eps^2, so each of its terms is m eps^-3 times an
+// exact zero: zero while m eps^-3 is finite in the pair arithmetic, NaN
+// (inf * 0) once it overflows, and 0 * inf with eps = 0. Below the limit
+// eps of self_mask_eps the pair is masked; at or above it the self term is
+// finite (an exact zero) for every mass below H6_SELF_MASK_MASS_F32 (the
+// FP32-range arithmetics mixed, EX, SP: eps^-3 <= 2^90) or
+// H6_SELF_MASK_MASS_F64 (FP64: eps^-3 <= 2^900).
+inline double self_mask_eps(int precision) {
+    return precision == H6_FP64 ? H6_SELF_MASK_EPS_F64 : H6_SELF_MASK_EPS_F32;
+}
 inline bool self_pair_masked(double eps2, int precision) {
-    if (precision == H6_FP64) return eps2 == 0.0;
-    return (float)eps2 < 1.17549435e-38f;  // below the smallest normal FP32
+    const double lim = self_mask_eps(precision);
+    return !(eps2 >= lim * lim);  // eps below the limit (0 included)
 }
 
 // ---- device-resident block loop (blockloop.hip)

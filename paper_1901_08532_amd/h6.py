@@ -124,6 +124,7 @@ _SIGS = {
     "h6_profile_read": (C.c_int, [C.c_void_p, C.POINTER(h6_eval_timing), C.c_int,
                                   C.POINTER(C.c_int)]),
     "h6_strerror": (C.c_char_p, [C.c_int]),
+    "h6_self_pair_masked": (C.c_int, [C.c_double, C.c_int]),
     "h6_last_error": (C.c_char_p, [C.c_void_p]),
 }
 

@@ -11,10 +11,15 @@
 
   python -m paper_1901_08532_amd.profsum traffic <fetch counter_collection.csv>
       <write counter_collection.csv> --copy-bytes B [--match SUBSTR] [--sources eval|vjp]
+      [--min-kib K]
       HBM bytes per dispatch of each matching kernel from FETCH_SIZE and
       WRITE_SIZE (KiB per dispatch), each scaled by the ratio of the known
       bytes a plain device copy of B bytes moves to what the same counter
-      reports for it. Prints key = value lines.
+      reports for it, averaged over the dispatches that fetched at least K
+      KiB (default 64: the loop's launches with nothing to do read a few
+      descriptor lines); the i-th dispatch of a kernel in the write run is
+      taken for the i-th of the fetch run (the runs are deterministic).
+      Prints key = value lines.
 """
 
 import argparse
@@ -62,23 +67,36 @@ def stats(path, match=None):
 
 
 def _counter_per_dispatch(path, counter):
-    """{kernel short name: [value per dispatch]} for one counter (summed over
-    the per-instance rows of a dispatch)."""
+    """{kernel short name: [value per dispatch, in dispatch order]} for one
+    counter (summed over the per-instance rows of a dispatch)."""
     per = defaultdict(float)
     names = {}
     for r in csv.DictReader(open(path)):
         if r.get("Counter_Name") != counter:
             continue
-        d = r["Dispatch_Id"]
+        d = int(r["Dispatch_Id"])
         per[d] += float(r["Counter_Value"])
         names[d] = _short(r["Kernel_Name"])
     by_kernel = defaultdict(list)
-    for d, v in per.items():
-        by_kernel[names[d]].append(v)
+    for d in sorted(per):
+        by_kernel[names[d]].append(per[d])
     return by_kernel
 
 
-def traffic(fetch_csv, write_csv, copy_bytes, match=None, sources="eval"):
+def _tag(k):
+    m = re.search(r"k_eval_f64<2, (\d+), (\d+), false>", k)
+    if m:
+        return "b%s_i%s" % (m.group(1), m.group(2))
+    for pat, tag in (("k_bl_eval<false, false>", "bl_eval_fp64"),
+                     ("k_bl_eval<true, false>", "bl_eval_mixed"),
+                     ("k_bl_finish", "bl_finish"),
+                     ("k_eval_vjp<2, 128, 0>", "eval_vjp")):
+        if pat in k:
+            return tag
+    return re.sub(r"\W+", "_", k)[:60]
+
+
+def traffic(fetch_csv, write_csv, copy_bytes, match=None, sources="eval", min_kib=64.0):
     fetch = _counter_per_dispatch(fetch_csv, "FETCH_SIZE")
     write = _counter_per_dispatch(write_csv, "WRITE_SIZE")
     # the calibration copy is the largest dispatch of a copy kernel in each run
@@ -99,21 +117,19 @@ def traffic(fetch_csv, write_csv, copy_bytes, match=None, sources="eval"):
         if match and match not in k:
             continue
         fv = fetch[k]
-        wv = write.get(k, [0.0])
-        fb = sum(fv) / len(fv) * 1024.0 * f_scale
-        wb = sum(wv) / len(wv) * 1024.0 * w_scale
-        m = re.search(r"k_eval_f64<2, (\d+), (\d+), false>", k)
-        if m:
-            tag = "b%s_i%s" % (m.group(1), m.group(2))
-        elif "k_bl_eval<false, false>" in k:
-            tag = "bl_eval_fp64"
-        elif "k_bl_eval<true, false>" in k:
-            tag = "bl_eval_mixed"
-        elif "k_eval_vjp<2, 128, 0>" in k:
-            tag = "eval_vjp"
-        else:
-            tag = re.sub(r"\W+", "_", k)[:60]
-        print("# %s: %d dispatches" % (k, len(fv)))
+        wv = write.get(k, [])
+        keep = [i for i, v in enumerate(fv) if v >= min_kib]
+        if not keep:
+            continue
+        fb = sum(fv[i] for i in keep) / len(keep) * 1024.0 * f_scale
+        if len(wv) == len(fv):
+            wb = sum(wv[i] for i in keep) / len(keep) * 1024.0 * w_scale
+        else:  # runs not aligned: every write dispatch
+            wb = sum(wv) / max(1, len(wv)) * 1024.0 * w_scale
+        tag = _tag(k)
+        print("# %s: %d dispatches, %d below %.0f KiB fetched (nothing to do) excluded"
+              % (k, len(fv), len(fv) - len(keep), min_kib))
+        print("dispatches_%s = %d" % (tag, len(keep)))
         print("fetch_bytes_per_launch_%s = %.1f" % (tag, fb))
         print("write_bytes_per_launch_%s = %.1f" % (tag, wb))
         print("hbm_bytes_per_launch_%s = %.1f" % (tag, fb + wb))
@@ -174,6 +190,7 @@ def main():
     b.add_argument("--match")
     b.add_argument("--sources", choices=("eval", "vjp"), default="eval",
                    help="which kernels' sources the record's hash covers")
+    b.add_argument("--min-kib", type=float, default=64.0)
     c = sub.add_parser("counters")
     c.add_argument("csv")
     c.add_argument("--match", required=True)
@@ -184,7 +201,8 @@ def main():
     elif args.cmd == "counters":
         counters(args.csv, args.match, args.interactions)
     else:
-        traffic(args.fetch_csv, args.write_csv, args.copy_bytes, args.match, args.sources)
+        traffic(args.fetch_csv, args.write_csv, args.copy_bytes, args.match, args.sources,
+                args.min_kib)
 
 
 if __name__ == "__main__":

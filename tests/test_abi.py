@@ -59,3 +59,43 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(h6, "LIB_PATH", "/nonexistent/libh6.so")
     with pytest.raises(h6.H6Error):
         h6.lib()
+
+
+def _self_term(m, eps, dtype):
+    # the self pair's acceleration term as the kernels form it: R^2 = eps^2,
+    # 1/R, 1/R^2, m/R^3, times the exact zero separation
+    import numpy as np
+
+    with np.errstate(over="ignore", invalid="ignore"):
+        e2 = dtype(eps) * dtype(eps)
+        rinv = dtype(1.0) / np.sqrt(e2)
+        mr3 = (dtype(m) * rinv) * (rinv * rinv)
+        return mr3 * dtype(0.0)
+
+
+def test_self_pair_mask_limits():
+    import numpy as np
+
+    L = h6.lib()
+    lim = {h6.H6_FP64: 2.0 ** -300, h6.H6_MIXED: 2.0 ** -30, h6.H6_EX: 2.0 ** -30,
+           h6.H6_SP: 2.0 ** -30}
+    for prec, e in lim.items():
+        assert L.h6_self_pair_masked(0.0, prec) == 1
+        assert L.h6_self_pair_masked(e * 0.5, prec) == 1
+        assert L.h6_self_pair_masked(e, prec) == 0
+        assert L.h6_self_pair_masked(1e-4, prec) == 0
+    # a softening of 1e-15 with a mass of 1e-3 overflows m eps^-3 in FP32:
+    # the FP32-range arithmetics mask it, FP64 need not
+    assert L.h6_self_pair_masked(1e-15, h6.H6_MIXED) == 1
+    assert L.h6_self_pair_masked(1e-15, h6.H6_FP64) == 0
+    assert L.h6_self_pair_masked(1e-104, h6.H6_FP64) == 1
+    assert L.h6_self_pair_masked(-1.0, h6.H6_FP64) == h6.H6_EINVAL
+    assert L.h6_self_pair_masked(float("inf"), h6.H6_FP64) == h6.H6_EINVAL
+    assert L.h6_self_pair_masked(1e-4, 99) == h6.H6_EINVAL
+    # at the limit the unmasked self term is an exact zero for every mass up
+    # to the stated bound (2^38 FP32, 2^124 FP64), and NaN just past it
+    for dtype, eps, mmax in ((np.float32, 2.0 ** -30, 2.0 ** 38),
+                             (np.float64, 2.0 ** -300, 2.0 ** 124)):
+        assert _self_term(mmax * 0.99, eps, dtype) == 0.0
+        assert np.isnan(_self_term(mmax * 4.0, eps, dtype))
+    assert np.isnan(_self_term(1e-3, 1e-15, np.float32))  # the failure masking avoids

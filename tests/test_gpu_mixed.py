@@ -110,34 +110,39 @@ def test_mixed_energy_drift_within_twice_fp64():
     assert drift[h6.H6_MIXED] <= 2.0 * drift[h6.H6_FP64], drift
 
 
+@pytest.mark.parametrize("eps", [1e-25, 1e-15])
 @pytest.mark.parametrize("prec", [h6.H6_MIXED, h6.H6_EX, h6.H6_SP])
-def test_fp32_arithmetics_mask_self_pair_when_softening_rounds_away(prec):
+def test_fp32_arithmetics_mask_self_pair_when_softening_is_tiny(prec, eps):
     # eps = 1e-25: eps^2 = 1e-50 is nonzero in FP64 but zero in FP32, so the
-    # self pair of the FP32-based arithmetics has r^2 = 0 and must be masked
-    # as with eps = 0; the results equal those at eps = 0 to the stated bound
+    # self pair of the FP32-based arithmetics has r^2 = 0; eps = 1e-15: eps^2
+    # is a normal FP32 number but m eps^-3 (masses near 1e-3) overflows it,
+    # and the self term would be inf * 0. Both are masked by index; the
+    # results equal the oracle's at that softening to the stated bound
     n = 1000
     x, v, _ = ics.plummer(n, 7)
     m = ics.salpeter_masses(n, 77)
+    assert h6.lib().h6_self_pair_masked(eps, prec) == 1
     a, _, _, _ = oracle.forces(x, v, m, 0.0, order=1)
     bound = {h6.H6_MIXED: BOUND, h6.H6_EX: {"a": 2e-12, "j": 4e-12, "s": 1e-11},
              h6.H6_SP: {"a": 1e-4, "j": 2e-4, "s": 5e-4}}[prec]
-    ctx = h6.Context(n, 1e-25)
+    ctx = h6.Context(n, eps)
     for act in (None, np.array([0, 5, 999], dtype=np.int32)):
         got = gpu_evaluate(ctx, x, v, a, m, active=act, precision=prec)
         idx = None if act is None else act.astype(np.int64)
-        want = oracle.forces(x, v, m, 1e-50, a=a, idx=idx, order=2)[:3]
+        want = oracle.forces(x, v, m, eps * eps, a=a, idx=idx, order=2)[:3]
         for name, g, w in zip("ajs", got, want):
             assert np.all(np.isfinite(g)), name
             assert vec_rel_err(g, w).max() <= bound[name], name
 
 
-def test_mixed_block_loop_with_vanishing_softening_stays_finite():
+@pytest.mark.parametrize("eps", [1e-25, 1e-15])
+def test_mixed_block_loop_with_vanishing_softening_stays_finite(eps):
     # the device-resident loop takes the same decision for its mixed kernels
     n = 512
     x, v, m = ics.plummer(n, 12)
     runs = {}
     for prec in (h6.H6_FP64, h6.H6_MIXED):
-        s = h6.System(x, v, m, 1e-25)
+        s = h6.System(x, v, m, eps)
         s.startup(eta_s=0.1, lev_min=4, lev_max=30)
         rc, st = s.run_blocks(1 << (h6.TICK_BITS - 6), 0.4, 4, 30, prec)
         assert rc == h6.H6_OK
