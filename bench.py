@@ -48,7 +48,7 @@ HBM_PEAK_GBPS = 8000.0
 MIXED_N = 262144
 MIXED_ACCURACY_TARGETS = 256
 TRAFFIC_INTERVALS = 16  # sync intervals the committed HBM-traffic record covers (the default --steps)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eval_hbm_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blockloop_n65536_hbm_traffic.txt")
 CSRC = os.path.join(ROOT, "paper_1901_08532_amd", "csrc")
 # the evaluation kernels' sources: the traffic record is void once any changes
 EVAL_SOURCES = ("eval_body.h", "eval_mixed_body.h", "device_math.h", "steps_body.h",
@@ -149,6 +149,13 @@ def main():
                     help="skip the mixed-vs-FP64 leg (power-law Plummer N = 262144, one sync interval each)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
+    ap.add_argument("--timed-only", action="store_true",
+                    help="only the timed window (for a profiler's per-kernel averages): no "
+                         "accuracy, single-pass, CPU-baseline, breakdown or mixed legs")
+    ap.add_argument("--slot-log", default=None, metavar="PATH",
+                    help="instead of the benchmark: one sync interval of the device loop with no "
+                         "event timing (for a kernel tracer), its slot log (n_act, split per "
+                         "slot) written to PATH")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -192,6 +199,8 @@ def main():
     rc = sysg.ctx.h6_check_status()
     if rc != h6.H6_OK:
         raise h6.H6Error(rc, "start-up")
+    if args.slot_log:
+        return _slot_log_interval(args, sysg, sync_ticks, eta, lev_min, lev_max, prec)
     S0, T0 = sysg.S.clone(), sysg.T.clone()
     e_start = sysg.energy()
     E0 = e_start[0] + e_start[1]
@@ -237,6 +246,7 @@ def main():
     inst = {}
     bins = {}
     empty_launches = 0
+    empty_ms = 0.0
     for p in evals:
         b = bins.setdefault(p["nact_log2"], {"launches": 0, "interactions": 0.0, "kernel_ms": 0.0})
         for f in ("launches", "interactions", "kernel_ms"):
@@ -245,6 +255,7 @@ def main():
             # launches enqueued past the last due block (bin -1) and those of
             # prediction slots (bin -2): nothing evaluated
             empty_launches += p["launches"]
+            empty_ms += p["kernel_ms"]
             continue
         key = (p["kind"], p["block"], p["ipl"])
         d = inst.setdefault(key, {"kind": p["kind"], "block": p["block"], "ipl": p["ipl"],
@@ -277,6 +288,11 @@ def main():
         "launches": dom["launches"],
         "empty_launches_excluded": empty_launches,
         "avg_launch_us": 1e3 * dom["kernel_ms"] / max(1, dom["launches"]),
+        # every dispatch of the kernel in the timed window, empty ones too (what
+        # a profiler's per-kernel average over the same window counts)
+        "dispatches_all": dom["launches"] + empty_launches,
+        "avg_dispatch_us_all": 1e3 * (dom["kernel_ms"] + empty_ms)
+                               / max(1, dom["launches"] + empty_launches),
         "flops_per_launch": FLOPS_PER_INTERACTION * dom["interactions"] / max(1, dom["launches"]),
         "algorithmic_bytes_per_launch": dom["bytes"] / max(1, dom["launches"]),
         "traffic_window": "per dispatch over %d timed sync intervals" % TRAFFIC_INTERVALS,
@@ -286,85 +302,85 @@ def main():
         roofline["executed_flops_per_interaction"] = xfl
         roofline["executed_tflops"] = achieved * xfl / FLOPS_PER_INTERACTION
 
-    # accuracy of the timed kernel itself: one more sync interval of the same
-    # loop (untimed), whose last block (every particle active) leaves its
-    # a, j, s in the state; the oracle evaluates sampled targets from that
-    # block's predicted arrays
-    rng = np.random.Generator(np.random.PCG64(7))
-    acc = _loop_accuracy(sysg, (args.steps + 1) * sync_ticks, eta, lev_min, lev_max, prec, m, eps,
-                         args.accuracy_targets, rng)
-    _log("accuracy of the loop's last block: a %.2e j %.2e s %.2e" % (
-        acc["max_rel_err_a"], acc["max_rel_err_j"], acc["max_rel_err_s"]))
+    acc = timings = cpu = step_roofs = mixed = None
+    if not args.timed_only:
+        # accuracy of the timed kernel itself: one more sync interval of the
+        # same loop (untimed), whose last block (every particle active)
+        # leaves its a, j, s in the state; the oracle evaluates sampled
+        # targets from that block's predicted arrays
+        rng = np.random.Generator(np.random.PCG64(7))
+        acc = _loop_accuracy(sysg, (args.steps + 1) * sync_ticks, eta, lev_min, lev_max, prec, m, eps,
+                             args.accuracy_targets, rng)
+        _log("accuracy of the loop's last block: a %.2e j %.2e s %.2e" % (
+            acc["max_rel_err_a"], acc["max_rel_err_j"], acc["max_rel_err_s"]))
 
-    # timings of single passes on the final, synchronised state, HIP events
-    # on the library's stream (torch's current one), mean of 10: (i) the
-    # a/j/s evaluation of all n particles with its slice reduction, (ii) a
-    # whole step of all n particles (predict, evaluate, reduce, correct)
-    reps = 10
-    Pt = sysg.S[0:9].contiguous()
-    Ft = torch.empty((9, n), dtype=torch.float64, device="cuda")
-    St = sysg.S.clone()
-    Pw = torch.empty((9, n), dtype=torch.float64, device="cuda")
+        # timings of single passes on the final, synchronised state, HIP events
+        # on the library's stream (torch's current one), mean of 10: (i) the
+        # a/j/s evaluation of all n particles with its slice reduction, (ii) a
+        # whole step of all n particles (predict, evaluate, reduce, correct)
+        reps = 10
+        Pt = sysg.S[0:9].contiguous()
+        Ft = torch.empty((9, n), dtype=torch.float64, device="cuda")
+        St = sysg.S.clone()
+        Pw = torch.empty((9, n), dtype=torch.float64, device="cuda")
 
-    def _events(fn):
-        fn()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
+        def _events(fn):
             fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return 1e3 * e0.elapsed_time(e1) / reps
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return 1e3 * e0.elapsed_time(e1) / reps
 
-    t_eval = _events(lambda: sysg.ctx.h6_evaluate(Pt, sysg.m, None, n, prec, Ft))
-    t_step = _events(lambda: sysg.ctx.h6_shared_steps(St, sysg.m, Pw, Ft, 2.0 ** -12, 1, prec))
-    timings = {
-        "eval_reduce_all_n_us": t_eval,
-        "eval_reduce_all_n_pct_fp64_peak": 100.0 * FLOPS_PER_INTERACTION * float(n) * n
-                                             / (t_eval * 1e-6) / (FP64_PEAK_TFLOPS * 1e12),
-        "step_all_n_us": t_step,
-        "block_step_avg_us": 1e6 * wall / max(1, blocks),
-        "run_s": wall,
-        "repeats": reps,
-    }
-    _log("eval+reduce of all %d: %.1f us; full step %.1f us" % (n, t_eval, t_step))
-
-    import oracle
-
-    P = sysg.S[0:9].contiguous()
-    xs, vs, as_ = (P[3 * k:3 * k + 3].T.cpu().numpy().copy() for k in range(3))
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        # the oracle's a/j/s evaluation of sampled targets against all n sources
-        probe = np.arange(0, n, max(1, n // 256))[:256]
-        tp = time.perf_counter()
-        oracle.forces(xs, vs, m, eps * eps, a=as_, idx=probe, order=2)
-        tp = time.perf_counter() - tp
-        n_i = int(min(n, max(256, len(probe) * args.cpu_seconds / max(tp, 1e-6))))
-        sample = np.sort(rng.choice(n, n_i, replace=False))
-        tc = time.perf_counter()
-        oracle.forces(xs, vs, m, eps * eps, a=as_, idx=sample, order=2)
-        tc = time.perf_counter() - tc
-        cpu = {
-            "value": n_i * n / tc,
-            "unit": "interactions/s",
-            "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "FP64 oracle a/j/s evaluation of %d sampled targets against all %d sources "
-                      "of the final synchronised state (%.1f s)" % (n_i, n, tc),
+        t_eval = _events(lambda: sysg.ctx.h6_evaluate(Pt, sysg.m, None, n, prec, Ft))
+        t_step = _events(lambda: sysg.ctx.h6_shared_steps(St, sysg.m, Pw, Ft, 2.0 ** -12, 1, prec))
+        timings = {
+            "eval_reduce_all_n_us": t_eval,
+            "eval_reduce_all_n_pct_fp64_peak": 100.0 * FLOPS_PER_INTERACTION * float(n) * n
+                                                 / (t_eval * 1e-6) / (FP64_PEAK_TFLOPS * 1e12),
+            "step_all_n_us": t_step,
+            "block_step_avg_us": 1e6 * wall / max(1, blocks),
+            "run_s": wall,
+            "repeats": reps,
         }
-        _log("cpu baseline: %.3e interactions/s on %d threads" % (cpu["value"], cpu["cores"]))
+        _log("eval+reduce of all %d: %.1f us; full step %.1f us" % (n, t_eval, t_step))
 
-    # the two kernels of every block, timed over the first sync interval
-    # again (untimed: events on every dispatch cost wall time)
-    sysg.S.copy_(S0)
-    sysg.T.copy_(T0)
-    step_roofs = _loop_breakdown(sysg, sync_ticks, eta, lev_min, lev_max, prec)
+        import oracle
 
-    mixed = None
-    if not args.no_mixed:
-        mixed = _mixed_vs_fp64(args, h6, ics, oracle)
+        P = sysg.S[0:9].contiguous()
+        xs, vs, as_ = (P[3 * k:3 * k + 3].T.cpu().numpy().copy() for k in range(3))
+
+        if not args.no_cpu_baseline:
+            # the oracle's a/j/s evaluation of sampled targets against all n sources
+            probe = np.arange(0, n, max(1, n // 256))[:256]
+            tp = time.perf_counter()
+            oracle.forces(xs, vs, m, eps * eps, a=as_, idx=probe, order=2)
+            tp = time.perf_counter() - tp
+            n_i = int(min(n, max(256, len(probe) * args.cpu_seconds / max(tp, 1e-6))))
+            sample = np.sort(rng.choice(n, n_i, replace=False))
+            tc = time.perf_counter()
+            oracle.forces(xs, vs, m, eps * eps, a=as_, idx=sample, order=2)
+            tc = time.perf_counter() - tc
+            cpu = {
+                "value": n_i * n / tc,
+                "unit": "interactions/s",
+                "cores": oracle.num_threads(),
+                "kind": "oracle",
+                "sample": "FP64 oracle a/j/s evaluation of %d sampled targets against all %d sources "
+                          "of the final synchronised state (%.1f s)" % (n_i, n, tc),
+            }
+            _log("cpu baseline: %.3e interactions/s on %d threads" % (cpu["value"], cpu["cores"]))
+
+        # the two kernels of every block, timed over the first sync interval
+        # again (untimed: events on every dispatch cost wall time)
+        sysg.S.copy_(S0)
+        sysg.T.copy_(T0)
+        step_roofs = _loop_breakdown(sysg, sync_ticks, eta, lev_min, lev_max, prec)
+
+        if not args.no_mixed:
+            mixed = _mixed_vs_fp64(args, h6, ics, oracle)
 
     out = {
         "metric": METRIC,
@@ -403,6 +419,36 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def _slot_log_interval(args, sysg, sync_ticks, eta, lev_min, lev_max, prec):
+    """One sync interval of the device loop under the slot log alone (no
+    events on the dispatches): writes one line "n_act split" per slot, in
+    launch order (each slot is one k_bl_eval and one k_bl_finish dispatch),
+    and prints a JSON line with the interval's blocks and wall time. The
+    first k_bl_eval dispatch of the process is this interval's first slot."""
+    import torch
+
+    from paper_1901_08532_amd import h6
+
+    sysg.ctx.h6_profile_enable(3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st = sysg.run_blocks(sync_ticks, eta, lev_min, lev_max, prec, check=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if rc != h6.H6_OK:
+        raise h6.H6Error(rc, "h6_run_blocks (slot log)")
+    slots = sysg.ctx.h6_profile_slots()
+    sysg.ctx.h6_profile_enable(False)
+    with open(args.slot_log, "w") as f:
+        f.write("# n_act split, one line per device-loop slot in launch order (split -1: "
+                "prediction slot; n_act 0: after the last due block)\n")
+        for na, sp in slots:
+            f.write("%d %d\n" % (na, sp))
+    print(json.dumps({"slot_log": args.slot_log, "slots": int(len(slots)), "blocks": st.blocks,
+                      "particle_steps": st.particle_steps, "wall_s": wall,
+                      "workload": args.workload, "n": sysg.n}), flush=True)
 
 
 def _loop_accuracy(sysg, t_end, eta, lev_min, lev_max, prec, m, eps, n_targets, rng):
@@ -493,7 +539,8 @@ def _loop_breakdown(sysg, sync_ticks, eta, lev_min, lev_max, prec):
     n_fin = sum(a["launches"] for a in fin)
     out["k_bl_finish"]["algorithmic_bytes_per_nonempty_launch"] = (
         sum(a["bytes"] for a in fin) / max(1, n_fin))
-    out["k_bl_finish"]["traffic_per_nonempty_launch"] = _traffic_per_launch("bl_finish")
+    out["k_bl_finish"]["traffic_per_nonempty_launch"] = _traffic_per_launch(
+        "bl_finish" + ("_mixed" if prec == h6.H6_MIXED else ""))
     out["k_bl_finish"]["traffic_window"] = "per dispatch over %d timed sync intervals" % TRAFFIC_INTERVALS
     return out
 

@@ -434,10 +434,22 @@ int h6_energy_vjp(h6_ctx ctx, const h6_state *st, int64_t n, const double *cot_e
  * durations are accumulated per kernel instantiation and per power-of-two
  * bin of the active-set size. on = 2 also times the device-resident loop's
  * finishing kernel of every block (records of kind 4, binned by the block's
- * active count like its evaluation). on = 0 turns the
- * hook off. Enabling clears the records. h6_profile_read (synchronizes)
- * copies up to max records to out and sets *count.
- * Errors: H6_EINVAL (on outside 0..2), H6_EHIP.
+ * active count like its evaluation). on = 3 records no events (nothing is
+ * added to the dispatches, for an external tracer) and keeps only the
+ * device-resident loop's slot log. on = 0 turns the hook off. Enabling
+ * clears the records. h6_profile_read (synchronizes) copies up to max
+ * records to out and sets *count.
+ * Errors: H6_EINVAL (on outside 0..3), H6_EHIP.
+ *
+ * h6_profile_slots (synchronizes): the slot log of the last device-loop
+ * h6_run_blocks call made with the hook on (any level): for each slot it
+ * enqueued, in launch order, one evaluation and one finishing dispatch, the
+ * pair (n_act, split) -- the slot's active count and source slices; split
+ * -1 marks a prediction slot (its evaluation does nothing, its finishing
+ * kernel predicts every particle to the planned block time), n_act 0 a
+ * slot after the last due block. Copies up to max pairs (2 max int32) to
+ * out and sets *count to the number of slots logged (the last 2^20 of the
+ * run). Errors: H6_EINVAL, H6_EHIP.
  */
 typedef struct {
     int order;      /* 2: per-step a/j/s; 1, 3: start-up passes */
@@ -469,6 +481,7 @@ typedef struct {
 
 int h6_profile_enable(h6_ctx ctx, int on);
 int h6_profile_read(h6_ctx ctx, h6_eval_timing *out, int max, int *count);
+int h6_profile_slots(h6_ctx ctx, int32_t *out, int max, int *count);
 
 /*
  * The self pair (a particle as its own source) contributes nothing; the

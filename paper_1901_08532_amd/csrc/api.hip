@@ -635,7 +635,7 @@ static int run_blocks_device(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred 
     A.eval_grid = bl_eval_grid(ctx);
     A.pc_pairs = (unsigned)(ctx->partial_cap / 9);
     A.flags = ctx->flags;
-    A.nact_log = ctx->prof ? ctx->bl_log : nullptr;
+    A.nact_log = ctx->prof_level > 0 ? ctx->bl_log : nullptr;
     A.log_mask = ctx->bl_log_mask;
     ctx->bl_n = n;
 
@@ -676,6 +676,7 @@ static int run_blocks_device(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred 
         }
     }
     H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    ctx->bl_slots = seq;
     // the copy enqueued last (or the set-up plan when nothing was due)
     const LoopDesc &d = have_prev ? *slot[cur] : *slot[0];
     if (!ctx->pending.empty()) H6_TRY(ctx, prof_resolve(ctx), "profile events");
@@ -900,7 +901,7 @@ int h6_init_forces_vjp(h6_ctx ctx, const h6_state *st, int64_t n, h6_state *cot)
 
 int h6_profile_enable(h6_ctx ctx, int on) {
     if (!ctx) return H6_EINVAL;
-    if (on < 0 || on > 2) return fail_arg(ctx, "bad profile level");
+    if (on < 0 || on > 3) return fail_arg(ctx, "bad profile level");
     H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
     H6_TRY(ctx, prof_resolve(ctx), "profile events");
     if (on && !ctx->bl_log) {
@@ -910,8 +911,30 @@ int h6_profile_enable(h6_ctx ctx, int on) {
         ctx->bl_log_mask = cap - 1;
     }
     ctx->timings.clear();
-    ctx->prof = on != 0;
+    ctx->prof = on == 1 || on == 2;
     ctx->prof_level = on;
+    ctx->bl_slots = 0;
+    return H6_OK;
+}
+
+int h6_profile_slots(h6_ctx ctx, int32_t *out, int max, int *count) {
+    if (!ctx || !count || max < 0 || (max > 0 && !out)) return fail_arg(ctx, "bad slot log read");
+    H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    const int64_t cap = ctx->bl_log ? (int64_t)ctx->bl_log_mask + 1 : 0;
+    const int64_t n = ctx->bl_slots < cap ? ctx->bl_slots : cap;
+    *count = (int)n;
+    if (n == 0 || max == 0) return H6_OK;
+    // the run's last n slots (slot s at ring entry s & mask)
+    std::vector<int32_t> ring(2 * (size_t)cap);
+    H6_TRY(ctx, hipMemcpy(ring.data(), ctx->bl_log, ring.size() * sizeof(int32_t),
+                          hipMemcpyDeviceToHost),
+           "slot log");
+    const int64_t first = ctx->bl_slots - n;
+    for (int64_t k = 0; k < n && k < max; ++k) {
+        const size_t e = 2 * (size_t)((first + k) & ctx->bl_log_mask);
+        out[2 * k] = ring[e];
+        out[2 * k + 1] = ring[e + 1];
+    }
     return H6_OK;
 }
 

@@ -210,17 +210,22 @@ __device__ __forceinline__ int fin_per_round(int split) {
 // waves in all. Tile kinds: kind 2 (up to kTile1Max targets) has 64 targets per one-wave
 // workgroup (one per lane), kind 0 128 (two per lane). The grid holds two
 // waves per SIMD, which share its issue rate, so a round of units is one
-// unit per SIMD. For a tile kind lane r - 1 (r = 1..8) prices the shape
-// whose units fill r rounds: the time in source rows of one unit is rounds
+// unit per SIMD. For a tile kind lanes r - 1 and r + 7 (r = 1..8) price
+// the shape whose units fill r rounds (the first with its slice count
+// rounded as below): the time in source rows of one unit is rounds
 // x slice length (a lone unit per SIMD issuing at about 3/4 of the rate of
 // two), plus the slice sums (72 bytes per slice and target, written, read
 // back and reduced: about 1/2400 row of a 64-target unit each); the
 // cheapest shape wins, ties going to fewer slices. pc_pairs bounds
-// split * n_act.
+// split * n_act. Slice counts from 8 up are rounded up to multiples of 8
+// (empty trailing slices) where the grid and pc_pairs allow, and for the
+// tile kinds where the price is within 2%: unit g * split + sl then runs on XCD
+// sl mod 8 for every target group g, so each XCD reads one eighth of the
+// sources.
 __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsigned pc_pairs) {
     const int lane = threadIdx.x & 63;
     const int pc = (int)(pc_pairs / (unsigned)n_act) > 0 ? (int)(pc_pairs / (unsigned)n_act) : 1;
-    int split, kind, groups;
+    int split, kind, groups, slice;
     if (n_act <= kSmall2Max) {
         kind = n_act <= kSmall1Max ? 1 : 3;
         groups = kind == 1 ? n_act : cdiv32(n_act, 2);
@@ -229,6 +234,10 @@ __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsig
         split = split < fit ? split : fit;
         split = split < pc ? split : pc;
         if (split < 1) split = 1;
+        slice = cdiv32(cdiv32(n, split), 64) * 64;
+        split = cdiv32(n, slice);
+        const int sp8 = (split + 7) & ~7;  // whole XCD classes (below)
+        if (split >= 8 && sp8 <= fit && sp8 <= pc) split = sp8;
     } else {
         const bool one = n_act <= kTile1Max;
         kind = one ? 2 : 0;
@@ -236,14 +245,18 @@ __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsig
         groups = cdiv32(n_act, tb);
         const int simds = eval_grid / 2;
         const int cap = cdiv32(n, 64) < pc ? cdiv32(n, 64) : pc;
-        int sp = 1;
+        int sp = 1, sl = 64;
         int64_t cost = INT64_MAX;
-        if (lane < 8) {
-            const int r = lane + 1;
+        if (lane < 16) {
+            const int r = (lane & 7) + 1;
             sp = (int)((int64_t)r * simds / groups);
             sp = sp < 1 ? 1 : (sp > cap ? cap : sp);
-            const int sl = cdiv32(cdiv32(n, sp), 64) * 64;
+            sl = cdiv32(cdiv32(n, sp), 64) * 64;
             sp = cdiv32(n, sl);
+            // lanes 0..7: a multiple of 8 slices (the last ones empty) when
+            // the partial buffer allows; lanes 8..15 the same shapes unrounded
+            const int sp8 = (sp + 7) & ~7;
+            if (lane < 8 && sp >= 8 && sp8 <= pc) sp = sp8;
             const int64_t units = (int64_t)groups * sp;
             cost = units <= simds ? (int64_t)sl + sl / 3 : ((units + simds - 1) / simds) * sl;
             cost += (int64_t)sp * n_act / (2400 * (tb / kTileBlock));
@@ -251,6 +264,8 @@ __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsig
             // 64-target unit)
             const int fr = cdiv32(cdiv32(n_act, fin_per_round(sp)), kFinGrid);
             cost += (int64_t)fr * 42 / (tb / kTileBlock);
+            // XCD-aligned slices win within 2% (fewer source re-reads)
+            if (lane < 8 && (sp & 7) == 0) cost -= cost / 50;
         }
         int64_t best = cost;
 #pragma unroll
@@ -259,16 +274,16 @@ __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsig
             best = o < best ? o : best;
         }
         // candidates' slice counts grow with r: the lowest lane at the
-        // minimum has the fewest slices
-        const unsigned long long at = __ballot(lane < 8 && cost == best);
+        // minimum has the fewest slices, rounded ones first
+        const unsigned long long at = __ballot(lane < 16 && cost == best);
         split = __shfl(sp, __builtin_ctzll(at), 64);
+        slice = __shfl(sl, __builtin_ctzll(at), 64);
     }
     if (lane != 0) return;
-    const int slice = cdiv32(cdiv32(n, split), 64) * 64;
     d->kind = kind;
     d->groups = groups;
     d->slice_len = slice;
-    d->split = cdiv32(n, slice);
+    d->split = split;
 }
 
 __device__ __forceinline__ int fin_workers(int n_act, int split) {
@@ -393,6 +408,24 @@ __device__ void plan_next(const LoopArgs &A, const LoopDesc *__restrict__ cur, c
     }
 }
 
+// Storage slot of slice sl of target group g in the wide slice-sum layout
+// ([k][c][slot]): the group's slices ordered by the XCD that computes them,
+// then by slice. Unit u = g * split + sl runs on workgroup u mod grid, which
+// the dispatcher places on XCD u mod 8 (round robin; the grid is a multiple
+// of 8), so consecutive slots -- the lines holding a target's slice sums --
+// are written through one XCD's L2 instead of partially through all eight.
+// A bijection of [0, split) for every g.
+__device__ __forceinline__ int xcd_slot(int g, int sl, int split) {
+    const int base = (int)(((int64_t)g * split) & 7);  // XCD of the group's slice 0
+    const int x = (base + sl) & 7;
+    int before = 0;  // the group's slices on lower XCDs
+    for (int y = 0; y < x; ++y) {
+        const int s0 = (y - base) & 7;  // the group's first slice on XCD y
+        before += s0 < split ? (split - 1 - s0) / 8 + 1 : 0;
+    }
+    return before + (sl - ((x - base) & 7)) / 8;
+}
+
 template <bool MIXED, bool SKIPSELF>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_bl_eval(
     LoopArgs A, int64_t seq) {
@@ -405,7 +438,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     // slice sums: with few slices (the finishing kernel gives each target a
     // thread) at partial[(sl * 9 + c) * n_act + k], consecutive targets
     // adjacent; with more (a wave per target) at partial[(k * 9 + c) * split
-    // + sl], a target's slices adjacent
+    // + xcd_slot(g, sl)], a target's slices adjacent
     const bool narrow = split <= kFinSplitNarrow;
     OutPtrs out;
 #pragma unroll
@@ -413,6 +446,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         out.p[c] = c < 9 ? A.partial + (int64_t)c * (narrow ? n_act : split) : nullptr;
     out.kstride = narrow ? 1 : (int64_t)9 * split;
     const int64_t slice_stride = narrow ? (int64_t)9 * n_act : 1;
+    // the output of unit (g, sl): the bodies write component c of target k
+    // at p[c][sl * slice_stride + k * kstride]; the wide layout's slot shift
+    // goes into the pointers
+    auto out_of = [&](int g, int sl) {
+        OutPtrs o = out;
+        if (!narrow) {
+            const int shift = xcd_slot(g, sl, split) - sl;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) o.p[c] += shift;
+        }
+        return o;
+    };
     const int units = groups * split;
     if ((int)blockIdx.x >= units) return;
     __shared__ RankTable rt;
@@ -430,21 +475,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         const ListPredSrc S{A, &rt};
         for (int u = blockIdx.x; u < units; u += gridDim.x) {
             const int g = u / split, sl = u - g * split;
+            const OutPtrs o = out_of(g, sl);
             if (kind == 0) {
                 if constexpr (MIXED)
                     mixed_tile_body<kTileBlock, kTileIpl, SKIPSELF>(S, A.n, n_act, A.eps2,
-                                                                    slice_len, out, slice_stride,
+                                                                    slice_len, o, slice_stride,
                                                                     g, sl, tile_m);
                 else
                     eval_tile_body<2, kTileBlock, kTileIpl, SKIPSELF, false>(
-                        S, A.n, n_act, A.eps2, slice_len, out, slice_stride, g, sl, tile);
+                        S, A.n, n_act, A.eps2, slice_len, o, slice_stride, g, sl, tile);
             } else {
                 if constexpr (MIXED)
                     mixed_tile_body<kTileBlock, 1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len,
-                                                             out, slice_stride, g, sl, tile_m);
+                                                             o, slice_stride, g, sl, tile_m);
                 else
                     eval_tile_body<2, kTileBlock, 1, SKIPSELF, true>(
-                        S, A.n, n_act, A.eps2, slice_len, out, slice_stride, g, sl, tile);
+                        S, A.n, n_act, A.eps2, slice_len, o, slice_stride, g, sl, tile);
             }
         }
         return;
@@ -453,19 +499,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         const ListPredSrc S{A, &rt};
         for (int u = blockIdx.x; u < units; u += gridDim.x) {
             const int g = u / split, sl = u - g * split;
+            const OutPtrs o = out_of(g, sl);
             if (kind == 1) {
                 if constexpr (MIXED)
-                    mixed_small_body<1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, out,
+                    mixed_small_body<1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, o,
                                                   slice_stride, g, sl, red);
                 else
-                    eval_small_body<1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, out,
+                    eval_small_body<1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, o,
                                                  slice_stride, g, sl, red);
             } else {
                 if constexpr (MIXED)
-                    mixed_small_body<2, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, out,
+                    mixed_small_body<2, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, o,
                                                   slice_stride, g, sl, red);
                 else
-                    eval_small_body<2, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, out,
+                    eval_small_body<2, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, o,
                                                  slice_stride, g, sl, red);
             }
         }

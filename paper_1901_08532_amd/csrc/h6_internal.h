@@ -167,8 +167,10 @@ struct h6_ctx_s {
         int kind;            // device loop: 2 evaluation, 3 predictor, 4 finishing kernel
         double bytes;        // algorithmic bytes (host-shaped evaluations)
     };
-    bool prof = false;
-    int prof_level = 0;  // 1: evaluation kernels; 2: also the device loop's other kernels
+    bool prof = false;   // event timing on (levels 1, 2)
+    int prof_level = 0;  // 1: evaluation kernels; 2: also the device loop's other kernels;
+                         // 3: no events, the device loop's slot log only
+    int64_t bl_slots = 0;  // slots the last device-loop run enqueued (slot log)
     std::vector<hipEvent_t> event_pool;
     std::vector<PendingTiming> pending;
     std::vector<h6_eval_timing> timings;

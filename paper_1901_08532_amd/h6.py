@@ -16,6 +16,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -123,6 +124,7 @@ _SIGS = {
     "h6_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "h6_profile_read": (C.c_int, [C.c_void_p, C.POINTER(h6_eval_timing), C.c_int,
                                   C.POINTER(C.c_int)]),
+    "h6_profile_slots": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
     "h6_strerror": (C.c_char_p, [C.c_int]),
     "h6_self_pair_masked": (C.c_int, [C.c_double, C.c_int]),
     "h6_last_error": (C.c_char_p, [C.c_void_p]),
@@ -375,7 +377,8 @@ class Context:
 
     def h6_profile_enable(self, on=True):
         """on: False/0 off, True/1 evaluation kernels, 2 also the device
-        loop's finishing kernels."""
+        loop's finishing kernels, 3 no events (the device loop's slot log
+        only)."""
         level = int(on) if not isinstance(on, bool) else (1 if on else 0)
         self._check(lib().h6_profile_enable(self._h, level), "h6_profile_enable")
 
@@ -387,6 +390,16 @@ class Context:
         self._check(lib().h6_profile_read(self._h, buf, cap, C.byref(cnt)), "h6_profile_read")
         return [{k: getattr(buf[q], k) for k, _ in h6_eval_timing._fields_}
                 for q in range(min(cnt.value, cap))]
+
+    def h6_profile_slots(self):
+        """(n_act, split) of every slot of the last device-loop run (profile
+        hook on), as an (S, 2) int32 array; split -1: a prediction slot."""
+        cnt = C.c_int()
+        self._check(lib().h6_profile_slots(self._h, None, 0, C.byref(cnt)), "h6_profile_slots")
+        out = np.zeros((max(cnt.value, 1), 2), dtype=np.int32)
+        self._check(lib().h6_profile_slots(self._h, out.ctypes.data, cnt.value, C.byref(cnt)),
+                    "h6_profile_slots")
+        return out[:cnt.value]
 
 
 class System:

@@ -20,6 +20,13 @@
       descriptor lines); the i-th dispatch of a kernel in the write run is
       taken for the i-th of the fetch run (the runs are deterministic).
       Prints key = value lines.
+
+  python -m paper_1901_08532_amd.profsum phases <kernel_trace.csv> <slot log>
+      the device loop's slots (bench.py --slot-log) joined with the kernel
+      trace of the same process (slot k: the k-th k_bl_eval and k_bl_finish
+      dispatches): per class of active count, the mean evaluation time, the
+      gap to the finishing kernel, the finishing time, the gap to the next
+      slot's evaluation, and the classes' shares of the interval
 """
 
 import argparse
@@ -135,6 +142,60 @@ def traffic(fetch_csv, write_csv, copy_bytes, match=None, sources="eval", min_ki
         print("hbm_bytes_per_launch_%s = %.1f" % (tag, fb + wb))
 
 
+def _slot_class(n_act, split):
+    if split < 0:
+        return "prediction slot"
+    if n_act == 0:
+        return "empty (after the last block)"
+    for hi, name in ((1, "1"), (2, "2"), (3, "3"), (15, "4-15"), (63, "16-63"), (511, "64-511"),
+                     (4095, "512-4095")):
+        if n_act <= hi:
+            return name
+    return "4096+"
+
+
+def phases(trace_csv, slot_log):
+    disp = []
+    for r in csv.DictReader(open(trace_csv)):
+        disp.append((int(r["Dispatch_Id"]), _short(r["Kernel_Name"]), int(r["Start_Timestamp"]),
+                     int(r["End_Timestamp"])))
+    disp.sort()
+    evals = [d for d in disp if d[1].startswith("h6::k_bl_eval")]
+    fins = [d for d in disp if d[1] == "h6::k_bl_finish"]
+    slots = [tuple(int(t) for t in line.split()) for line in open(slot_log)
+             if line.strip() and not line.startswith("#")]
+    if not (len(evals) == len(fins) == len(slots)):
+        raise SystemExit("dispatches (%d evaluations, %d finishing) and slots (%d) differ"
+                         % (len(evals), len(fins), len(slots)))
+    order = ["1", "2", "3", "4-15", "16-63", "64-511", "512-4095", "4096+", "prediction slot",
+             "empty (after the last block)"]
+    acc = {c: [0, 0.0, 0.0, 0.0, 0.0, 0.0] for c in order}
+    t_first, t_last = evals[0][2], fins[-1][3]
+    for k, ((na, sp), e, f) in enumerate(zip(slots, evals, fins)):
+        nxt = evals[k + 1][2] if k + 1 < len(evals) else f[3]
+        a = acc[_slot_class(na, sp)]
+        a[0] += 1
+        a[1] += (e[3] - e[2]) * 1e-3
+        a[2] += (f[2] - e[3]) * 1e-3
+        a[3] += (f[3] - f[2]) * 1e-3
+        a[4] += (nxt - f[3]) * 1e-3
+        a[5] += (nxt - e[2]) * 1e-3
+    total = (t_last - t_first) * 1e-3
+    print("# %d slots, %.3f ms from the first evaluation's start to the last finishing "
+          "kernel's end" % (len(slots), total * 1e-3))
+    print("%-28s %7s %9s %9s %9s %9s %9s %7s" % ("active count", "slots", "eval_us", "gap1_us",
+                                                  "finish_us", "gap2_us", "slot_us", "share"))
+    for c in order:
+        a = acc[c]
+        if not a[0]:
+            continue
+        m = [v / a[0] for v in a[1:]]
+        print("%-28s %7d %9.2f %9.2f %9.2f %9.2f %9.2f %6.1f%%" % (c, a[0], *m, 100 * a[5] / total))
+    print("# eval: k_bl_eval duration; gap1: its end to the finishing kernel's start; finish:")
+    print("# k_bl_finish duration; gap2: its end to the next slot's evaluation start; slot: from")
+    print("# this slot's evaluation start to the next one's (all means per slot, microseconds)")
+
+
 def counters(path, match, interactions):
     """Per-dispatch counters of the largest dispatches of a kernel (by
     SQ_INSTS_VALU_FMA_F64), as instructions per interaction for a dispatch
@@ -191,6 +252,9 @@ def main():
     b.add_argument("--sources", choices=("eval", "vjp"), default="eval",
                    help="which kernels' sources the record's hash covers")
     b.add_argument("--min-kib", type=float, default=64.0)
+    ph = sub.add_parser("phases")
+    ph.add_argument("trace_csv")
+    ph.add_argument("slot_log")
     c = sub.add_parser("counters")
     c.add_argument("csv")
     c.add_argument("--match", required=True)
@@ -200,6 +264,8 @@ def main():
         stats(args.csv, args.match)
     elif args.cmd == "counters":
         counters(args.csv, args.match, args.interactions)
+    elif args.cmd == "phases":
+        phases(args.trace_csv, args.slot_log)
     else:
         traffic(args.fetch_csv, args.write_csv, args.copy_bytes, args.match, args.sources,
                 args.min_kib)

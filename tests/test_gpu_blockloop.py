@@ -181,6 +181,33 @@ def test_device_loop_profile_records_of_both_kernels():
     assert by_kind[2][2] >= 80.0 * n * st.blocks + 76.0 * st.particle_steps
 
 
+def test_slot_log_accounts_for_every_block():
+    # profile level 3: no events, the slot log only. Every block appears once
+    # with its active count, prediction slots carry the count of the block
+    # they precede, and the run's first slot is one (its set-up makes no guess)
+    n = 8192
+    x, v, m = ics.plummer(n, 13)
+    s = h6.System(x, v, m, EPS)
+    s.startup(eta_s=0.1, lev_min=4, lev_max=30)
+    s.ctx.h6_profile_enable(3)
+    rc, st = s.run_blocks(SYNC, 0.4, 4, 30)
+    slots = s.ctx.h6_profile_slots()
+    assert s.ctx.h6_profile_read() == []  # no event records at this level
+    s.ctx.h6_profile_enable(False)
+    assert rc == h6.H6_OK
+    na, sp = slots[:, 0], slots[:, 1]
+    blocks = (na > 0) & (sp > 0)
+    assert int(blocks.sum()) == st.blocks
+    assert int(na[blocks].sum()) == st.particle_steps
+    assert sp[0] == -1 and na[0] > 0
+    pslots = np.nonzero(sp < 0)[0]
+    assert np.all(pslots + 1 < len(slots))
+    assert np.array_equal(na[pslots], na[pslots + 1]) and np.all(sp[pslots + 1] > 0)
+    # after the last block only empty slots (batch overshoot)
+    last = np.nonzero(blocks)[0][-1]
+    assert np.all(na[last + 1:] == 0)
+
+
 def _host_vs_device(s_dev, s_host, t_end, lev_min, lev_max):
     rd, sd = s_dev.run_blocks(t_end, 0.4, lev_min, lev_max)
     rh, sh = s_host.run_blocks(t_end, 0.4, lev_min, lev_max, host_loop=True)
@@ -283,7 +310,7 @@ def _one_block_against_host_loop_and_oracle(n, n_act, precision, seed=21, sample
 def test_device_loop_tile_units_beyond_the_grid(precision, n_act):
     # one block of n_act of 65536 particles: the device loop cuts the sources
     # into more tile units (target group x slice) than it launches workgroups
-    # (3008 and 6880 units for 2048 workgroups), which take them in rounds.
+    # (3008 and 7912 units for 2048 workgroups), which take them in rounds.
     # Every unit must be evaluated exactly once.
     _one_block_against_host_loop_and_oracle(65536, n_act, precision)
 
