@@ -110,7 +110,7 @@ struct RankTable {
 // start (one round trip to memory instead of one per dependent branch);
 // thread t < kLevels also takes off[t] and cnt[t]. Needs blockDim.x >= kLevels.
 struct DescHead {
-    int64_t t_next;
+    int64_t t_next, blocks, particle_steps;
     unsigned long long sel;
     int n_act, split, slice_len, groups, kind, L0, lv_hi, pred_ok;
     int my_off, my_cnt;
@@ -118,6 +118,8 @@ struct DescHead {
 __device__ __forceinline__ DescHead load_head(const LoopDesc *__restrict__ d) {
     DescHead h;
     h.t_next = d->t_next;
+    h.blocks = d->blocks;
+    h.particle_steps = d->particle_steps;
     h.sel = d->sel;
     h.n_act = d->n_act;
     h.split = d->split;
@@ -205,9 +207,9 @@ __device__ __forceinline__ int fin_per_round(int split) {
                                    : kFinThreads / fin_seg(split);
 }
 // Evaluation shape for n_act targets, chosen by one wave (every lane calls
-// it, lane 0 writes *d). Source-parallel kinds (1: one target per wave, 3:
-// two): slices of at least 256 sources (4 per lane), at most eval_grid
-// waves in all. Tile kinds: kind 2 (up to kTile1Max targets) has 64 targets per one-wave
+// it, lane 0 writes *d; every lane gets the slice count back).
+// Source-parallel kinds (1: one target per wave, 3: two): slices of at least
+// 256 sources (4 per lane), at most eval_grid waves in all. Tile kinds: kind 2 (up to kTile1Max targets) has 64 targets per one-wave
 // workgroup (one per lane), kind 0 128 (two per lane). The grid holds two
 // waves per SIMD, which share its issue rate, so a round of units is one
 // unit per SIMD. For a tile kind lanes r - 1 and r + 7 (r = 1..8) price
@@ -222,7 +224,7 @@ __device__ __forceinline__ int fin_per_round(int split) {
 // tile kinds where the price is within 2%: unit g * split + sl then runs on XCD
 // sl mod 8 for every target group g, so each XCD reads one eighth of the
 // sources.
-__device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsigned pc_pairs) {
+__device__ int launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsigned pc_pairs) {
     const int lane = threadIdx.x & 63;
     const int pc = (int)(pc_pairs / (unsigned)n_act) > 0 ? (int)(pc_pairs / (unsigned)n_act) : 1;
     int split, kind, groups, slice;
@@ -246,10 +248,13 @@ __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsig
         const int simds = eval_grid / 2;
         const int cap = cdiv32(n, 64) < pc ? cdiv32(n, 64) : pc;
         int sp = 1, sl = 64;
-        int64_t cost = INT64_MAX;
+        // prices in float (32-bit arithmetic only: 64-bit divisions expand to
+        // long sequences on this GPU, and the planner is on every block's
+        // critical path); the same inputs give the same shape on every run
+        float cost = 3.0e38f;
         if (lane < 16) {
             const int r = (lane & 7) + 1;
-            sp = (int)((int64_t)r * simds / groups);
+            sp = r * simds / groups;
             sp = sp < 1 ? 1 : (sp > cap ? cap : sp);
             sl = cdiv32(cdiv32(n, sp), 64) * 64;
             sp = cdiv32(n, sl);
@@ -257,20 +262,22 @@ __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsig
             // the partial buffer allows; lanes 8..15 the same shapes unrounded
             const int sp8 = (sp + 7) & ~7;
             if (lane < 8 && sp >= 8 && sp8 <= pc) sp = sp8;
-            const int64_t units = (int64_t)groups * sp;
-            cost = units <= simds ? (int64_t)sl + sl / 3 : ((units + simds - 1) / simds) * sl;
-            cost += (int64_t)sp * n_act / (2400 * (tb / kTileBlock));
+            const int units = groups * sp;  // below 2^27 (pc_pairs bounds sp * n_act)
+            const float ipl = (float)(tb / kTileBlock);
+            cost = units <= simds ? (float)sl * (4.0f / 3.0f)
+                                  : ceilf((float)units / (float)simds) * (float)sl;
+            cost += (float)sp * (float)n_act / (2400.0f * ipl);
             // the finishing kernel's rounds, each about 10 us (42 rows of a
             // 64-target unit)
-            const int fr = cdiv32(cdiv32(n_act, fin_per_round(sp)), kFinGrid);
-            cost += (int64_t)fr * 42 / (tb / kTileBlock);
+            const float fr = ceilf(ceilf((float)n_act / (float)fin_per_round(sp)) / (float)kFinGrid);
+            cost += fr * 42.0f / ipl;
             // XCD-aligned slices win within 2% (fewer source re-reads)
-            if (lane < 8 && (sp & 7) == 0) cost -= cost / 50;
+            if (lane < 8 && (sp & 7) == 0) cost *= 0.98f;
         }
-        int64_t best = cost;
+        float best = cost;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
-            const int64_t o = __shfl_xor(best, off, 64);
+            const float o = __shfl_xor(best, off, 64);
             best = o < best ? o : best;
         }
         // candidates' slice counts grow with r: the lowest lane at the
@@ -279,11 +286,13 @@ __device__ void launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsig
         split = __shfl(sp, __builtin_ctzll(at), 64);
         slice = __shfl(sl, __builtin_ctzll(at), 64);
     }
-    if (lane != 0) return;
-    d->kind = kind;
-    d->groups = groups;
-    d->slice_len = slice;
-    d->split = split;
+    if (lane == 0) {
+        d->kind = kind;
+        d->groups = groups;
+        d->slice_len = slice;
+        d->split = split;
+    }
+    return split;
 }
 
 __device__ __forceinline__ int fin_workers(int n_act, int split) {
@@ -297,8 +306,8 @@ __device__ __forceinline__ int fin_workers(int n_act, int split) {
 // evaluation shape; n_act = 0 and done = 1 once t_next would pass t_end.
 // t_spec: the time every particle was predicted to (-1: none), which makes
 // the plan's pred_ok.
-// One wave (all 64 lanes call it), lane L for level L: a wave minimum gives
-// t_next, a ballot the occupied levels, a suffix scan the rank offsets.
+// One wave (all 64 lanes call it), lane L for level L: a ballot gives the
+// occupied levels and t_next, a suffix scan the rank offsets.
 __device__ void plan_block(const LoopArgs &A, LoopDesc *d, const int *cnt, int64_t t_cur,
                            uint64_t sel, int64_t blocks, int64_t psteps, int64_t seq_next,
                            int64_t t_spec) {
@@ -306,19 +315,17 @@ __device__ void plan_block(const LoopArgs &A, LoopDesc *d, const int *cnt, int64
     const int L = threadIdx.x & 63;
     const bool listed = L >= A.lev_lo && L < A.lev_lo + A.nl;
     const int c = listed ? cnt[L] : 0;
-    // next multiple of 2^(40 - L) ticks after t_cur (t_cur >= 0)
-    int64_t tn = INT64_MAX;
-    if (c > 0) {
-        const int sh = kTickBits - L;
-        tn = ((t_cur >> sh) + 1) << sh;
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const int64_t o = __shfl_xor(tn, off, 64);
-        tn = o < tn ? o : tn;
-    }
     const unsigned long long occ = __ballot(c > 0);
     const int lv_hi = occ ? 63 - __builtin_clzll(occ) : -1;
+    // the earliest of the occupied levels' next due times after t_cur
+    // (t_cur >= 0): that of the highest level, the next multiple of its step
+    // 2^(40 - lv_hi) ticks -- every coarser step is a multiple of it, so a
+    // coarser level's next multiple is never earlier
+    int64_t tn = INT64_MAX;
+    if (lv_hi >= 0) {
+        const int sh = kTickBits - lv_hi;
+        tn = ((t_cur >> sh) + 1) << sh;
+    }
     const bool done = lv_hi < 0 || tn > A.t_end;
     int L0 = done ? lv_hi : kTickBits - __builtin_ctzll((unsigned long long)tn);
     if (!done && L0 < A.lev_lo) L0 = A.lev_lo;
@@ -332,7 +339,7 @@ __device__ void plan_block(const LoopArgs &A, LoopDesc *d, const int *cnt, int64
     }
     const int n_act = __shfl(incl, 0, 64);
     if (!done && L >= L0 && L <= lv_hi) d->off[L] = incl - mine;
-    if (!done) launch_shape(d, A.n, n_act, A.eval_grid, A.pc_pairs);  // the whole wave
+    const int split = done ? 0 : launch_shape(d, A.n, n_act, A.eval_grid, A.pc_pairs);  // the whole wave
     if (L != 0) return;
     d->t_next = tn;
     d->lv_hi = lv_hi;
@@ -354,7 +361,7 @@ __device__ void plan_block(const LoopArgs &A, LoopDesc *d, const int *cnt, int64
     if (A.nact_log) {
         int32_t *e = A.nact_log + 2 * (seq_next & A.log_mask);
         e[0] = n_act;
-        e[1] = done ? 0 : (pred_ok ? d->split : -1);
+        e[1] = done ? 0 : (pred_ok ? split : -1);
     }
 }
 
@@ -366,16 +373,17 @@ struct Tally {
     unsigned app;
 };
 
-// Level counts after block `cur` (cur_cnt: its counts, in LDS; the rebuilt
+// Level counts after block `cur` (its descriptor head as loaded at the
+// kernel's start; cur_cnt: its counts, in LDS; the rebuilt
 // lists of the active levels; the appended particles of level L0 - 1), then
 // the plan of the next block into *dn. The whole workgroup, after every list
-// update of the block: one thread per level gathers, one thread plans from
+// update of the block: one thread per level gathers, one wave plans from
 // LDS. solo: the tallies are this workgroup's (LDS), else the device's.
-__device__ void plan_next(const LoopArgs &A, const LoopDesc *__restrict__ cur, const int *cur_cnt,
+__device__ void plan_next(const LoopArgs &A, const DescHead &cur, const int *cur_cnt,
                           const Tally *solo, LoopDesc *dn, int64_t seq, int64_t t_spec) {
     __shared__ int s_cnt[kLevels];
     LoopScratch *scr = A.scr;
-    const int L0 = cur->L0;
+    const int L0 = cur.L0;
     for (int L = threadIdx.x; L < kLevels; L += blockDim.x) {
         int c = cur_cnt[L];
         if (L >= A.lev_lo && L < A.lev_lo + A.nl) {
@@ -403,7 +411,7 @@ __device__ void plan_next(const LoopArgs &A, const LoopDesc *__restrict__ cur, c
         // list buffers flip for the active levels [max(L0, lev_lo), lev_lo + nl)
         const int lo = L0 > A.lev_lo ? L0 : A.lev_lo;
         const uint64_t flip = ((1ull << (A.lev_lo + A.nl)) - 1ull) & ~((1ull << lo) - 1ull);
-        plan_block(A, dn, s_cnt, cur->t_next, cur->sel ^ flip, cur->blocks, cur->particle_steps,
+        plan_block(A, dn, s_cnt, cur.t_next, cur.sel ^ flip, cur.blocks, cur.particle_steps,
                    seq + 1, t_spec);
     }
 }
@@ -587,7 +595,7 @@ __device__ __forceinline__ void fin_wide_sums(const double *__restrict__ part, i
                                               int split, double2 *gsum, double *fs,
                                               PARTICLE particle) {
     constexpr int G = kFinGroups * WPT;
-    constexpr int U = 16;
+    constexpr int U = 19;  // two batches hold the 37 slices per lane of split <= 256 * WPT
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int r = w / WPT, pw = w % WPT;
     const int c = lane / kFinGroups, g = lane % kFinGroups;
@@ -601,18 +609,22 @@ __device__ __forceinline__ void fin_wide_sums(const double *__restrict__ part, i
 #pragma unroll
         for (int u = 0; u < U; ++u) x[u] = i0 + u < nq ? pc[G * (i0 + u)] : 0.0;
     };
-    // the first slices, then the particle and its old state (list, then
-    // state: two dependent loads), all in flight together
+    // two batches of slices and the particle's list entry in flight
+    // together, then its old state (dependent on the list entry) while the
+    // batches are summed: two memory round trips in all
     const int nq_max = (split + G - 1) / G;
     load(xa, 0);
+    if (U < nq_max) load(xb, U);
     particle();
     double hs = 0.0, hc = 0.0;
     for (int i0 = 0; i0 < nq_max; i0 += 2 * U) {
-        if (i0 + U < nq_max) load(xb, i0 + U);
+        if (i0 > 0) {
+            load(xa, i0);
+            if (i0 + U < nq_max) load(xb, i0 + U);
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) two_sum_into(hs, hc, xa[u]);
         if (i0 + U >= nq_max) break;
-        if (i0 + 2 * U < nq_max) load(xa, i0 + 2 * U);
 #pragma unroll
         for (int u = 0; u < U; ++u) two_sum_into(hs, hc, xb[u]);
     }
@@ -750,11 +762,11 @@ __device__ __forceinline__ void finish_targets(const LoopArgs &A, const DescHead
         }
     }
     if (solo) {
-        plan_next(A, d, cur_cnt, tally, dn, seq, t_spec);
+        plan_next(A, h, cur_cnt, tally, dn, seq, t_spec);
         return;
     }
     if (!arrive_last(&A.scr->done_fin, (unsigned)workers)) return;
-    plan_next(A, d, cur_cnt, nullptr, dn, seq, t_spec);
+    plan_next(A, h, cur_cnt, nullptr, dn, seq, t_spec);
 }
 
 // Prediction to t_to of the particles not due in the block (all of them in
