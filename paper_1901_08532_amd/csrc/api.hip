@@ -596,7 +596,8 @@ static int run_blocks_host(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *p
 // block 0 (one readback: a state off the block grid goes to the host loop);
 // then blocks are enqueued in batches, and after enqueueing batch b the host
 // waits for batch b-1 and reads its descriptor copy, so the device always
-// has a batch queued. Blocks enqueued after the last one due are no-ops.
+// has a batch queued. Slots enqueued after the last block due are no-ops;
+// batch sizes are capped by an estimate of the slots left, so that few are.
 static int run_blocks_device(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred *pred,
                              const h6_force *f, int32_t *active, const h6_params *prm,
                              int64_t t_end, h6_run_stats *stats) {
@@ -648,26 +649,54 @@ static int run_blocks_device(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred 
            "block plan readback");
     H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
     if (slot[0]->invalid) return run_blocks_host(ctx, st, n, pred, f, active, prm, t_end, stats);
+    // Slots still to come after a plan, estimated from its time and highest
+    // occupied level: were that level to stay the highest, the blocks come
+    // one of its steps apart until t_end; a sixteenth more for prediction
+    // slots. More blocks than that (a finer level appearing) only cost a
+    // host round trip before the next batch; fewer leave empty slots.
+    auto est_slots = [&](const LoopDesc &p) -> int64_t {
+        if (p.done || p.lv_hi < 0) return 0;
+        const int64_t r = ((t_end - p.t_next) >> (kTickBits - p.lv_hi)) + 1;
+        return r + r / 16 + 1;
+    };
     int64_t seq = 0;
-    int cur = 0;
-    bool have_prev = false;
+    int next = 0;               // readback slot of the next batch
+    int last = 0;               // readback slot enqueued last (0: the set-up plan)
+    bool pending = false;       // a batch is queued whose plan copy is unread
+    int pend = 0;               // its readback slot
+    int64_t pend_slots = 0;     // and its size
     bool done = slot[0]->done != 0;
+    int64_t est = est_slots(*slot[0]);
     int batch = 4;
     while (!done) {
-        for (int b = 0; b < batch; ++b, ++seq)
+        int64_t room = est - (pending ? pend_slots : 0);
+        if (room <= 0 && pending) {
+            // the queued batch should end the run: wait for it first
+            H6_TRY(ctx, hipEventSynchronize(ctx->bl_ev[pend]), "event wait");
+            pending = false;
+            done = slot[pend]->done != 0;
+            est = est_slots(*slot[pend]);
+            continue;
+        }
+        const int nb = (int)(room < 1 ? 1 : (room < batch ? room : batch));
+        for (int b = 0; b < nb; ++b, ++seq)
             H6_TRY(ctx, bl_enqueue_block(ctx, A, prm->precision, seq), "block step");
         // plan of the block after the batch: done once nothing is due before t_end
         H6_TRY(ctx,
-               hipMemcpyAsync(slot[cur], ctx->bl_desc + (seq & 1), sizeof(LoopDesc),
+               hipMemcpyAsync(slot[next], ctx->bl_desc + (seq & 1), sizeof(LoopDesc),
                               hipMemcpyDeviceToHost, ctx->stream),
                "block status readback");
-        H6_TRY(ctx, hipEventRecord(ctx->bl_ev[cur], ctx->stream), "event record");
-        if (have_prev) {
-            H6_TRY(ctx, hipEventSynchronize(ctx->bl_ev[cur ^ 1]), "event wait");
-            if (slot[cur ^ 1]->done) break;
+        H6_TRY(ctx, hipEventRecord(ctx->bl_ev[next], ctx->stream), "event record");
+        last = next;
+        if (pending) {
+            H6_TRY(ctx, hipEventSynchronize(ctx->bl_ev[pend]), "event wait");
+            if (slot[pend]->done) break;  // the batch just queued finds nothing to do
+            est = est_slots(*slot[pend]);
         }
-        have_prev = true;
-        cur ^= 1;
+        pending = true;
+        pend = next;
+        pend_slots = nb;
+        next ^= 1;
         if (batch < 64) batch *= 2;
         if (ctx->prof && (int64_t)ctx->pending.size() > (int64_t)(ctx->bl_log_mask / 2)) {
             // resolve before the block log ring wraps
@@ -678,7 +707,7 @@ static int run_blocks_device(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred 
     H6_TRY(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
     ctx->bl_slots = seq;
     // the copy enqueued last (or the set-up plan when nothing was due)
-    const LoopDesc &d = have_prev ? *slot[cur] : *slot[0];
+    const LoopDesc &d = *slot[last];
     if (!ctx->pending.empty()) H6_TRY(ctx, prof_resolve(ctx), "profile events");
     if (stats) {
         stats->blocks = d.blocks;
