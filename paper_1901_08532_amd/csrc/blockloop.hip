@@ -274,17 +274,15 @@ __device__ int launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsign
             // XCD-aligned slices win within 2% (fewer source re-reads)
             if (lane < 8 && (sp & 7) == 0) cost *= 0.98f;
         }
-        float best = cost;
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            const float o = __shfl_xor(best, off, 64);
-            best = o < best ? o : best;
-        }
-        // candidates' slice counts grow with r: the lowest lane at the
-        // minimum has the fewest slices, rounded ones first
-        const unsigned long long at = __ballot(lane < 16 && cost == best);
-        split = __shfl(sp, __builtin_ctzll(at), 64);
-        slice = __shfl(sl, __builtin_ctzll(at), 64);
+        // the cheapest of the 16 candidates (lanes 0..15, one DPP row): the
+        // costs are positive, so their bit patterns order like the values;
+        // the low 4 bits carry the lane, so ties go to the lowest lane (the
+        // candidates' slice counts grow with r: the fewest slices, rounded
+        // ones first)
+        const unsigned key = (__float_as_uint(cost) & ~15u) | (unsigned)(lane & 15);
+        const int win = (int)(__builtin_amdgcn_readfirstlane(row_min_u32(key)) & 15u);
+        split = __builtin_amdgcn_readlane(sp, win);
+        slice = __builtin_amdgcn_readlane(sl, win);
     }
     if (lane == 0) {
         d->kind = kind;
@@ -307,7 +305,7 @@ __device__ __forceinline__ int fin_workers(int n_act, int split) {
 // t_spec: the time every particle was predicted to (-1: none), which makes
 // the plan's pred_ok.
 // One wave (all 64 lanes call it), lane L for level L: a ballot gives the
-// occupied levels and t_next, a suffix scan the rank offsets.
+// occupied levels and t_next, per-lane sums over LDS the rank offsets.
 __device__ void plan_block(const LoopArgs &A, LoopDesc *d, const int *cnt, int64_t t_cur,
                            uint64_t sel, int64_t blocks, int64_t psteps, int64_t seq_next,
                            int64_t t_spec) {
@@ -329,16 +327,14 @@ __device__ void plan_block(const LoopArgs &A, LoopDesc *d, const int *cnt, int64
     const bool done = lv_hi < 0 || tn > A.t_end;
     int L0 = done ? lv_hi : kTickBits - __builtin_ctzll((unsigned long long)tn);
     if (!done && L0 < A.lev_lo) L0 = A.lev_lo;
-    // ranks run over the active levels from the highest down
-    const int mine = (!done && L >= L0) ? c : 0;
-    int incl = mine;  // sum over levels >= L
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int o = __shfl_down(incl, off, 64);
-        if (L + off < 64) incl += o;
-    }
-    const int n_act = __shfl(incl, 0, 64);
-    if (!done && L >= L0 && L <= lv_hi) d->off[L] = incl - mine;
+    // ranks run over the active levels from the highest down: lane L of an
+    // active level sums the counts of the levels L .. lv_hi (all listed)
+    const bool act = !done && L >= L0 && L <= lv_hi;
+    int incl = 0;
+    if (act)
+        for (int l = L; l <= lv_hi; ++l) incl += cnt[l];
+    const int n_act = done ? 0 : __builtin_amdgcn_readlane(incl, L0);
+    if (act) d->off[L] = incl - c;
     const int split = done ? 0 : launch_shape(d, A.n, n_act, A.eval_grid, A.pc_pairs);  // the whole wave
     if (L != 0) return;
     d->t_next = tn;

@@ -137,6 +137,24 @@ __device__ __forceinline__ void seg_comp_reduce_n(double *s, double *c, int seg)
     if (seg >= 64) bcast_stage<NV, 0x143, 0xC>(s, c);  // row_bcast:31 into rows 2, 3
 }
 
+// Minimum of a 32-bit unsigned over each 16-lane row, by four DPP stages
+// (the two quad permutations, then the half-row and row mirrors, which pair
+// the halves of each group of 8, then 16 lanes once every lane of a half
+// holds its half's minimum); every lane of a row ends with the row's
+// minimum. All lanes of the wave must be active.
+__device__ __forceinline__ unsigned row_min_u32(unsigned v) {
+    int o;
+    o = __builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    v = (unsigned)o < v ? (unsigned)o : v;
+    o = __builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    v = (unsigned)o < v ? (unsigned)o : v;
+    o = __builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    v = (unsigned)o < v ? (unsigned)o : v;
+    o = __builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);  // row_mirror
+    v = (unsigned)o < v ? (unsigned)o : v;
+    return v;
+}
+
 // Totals over the 64 lanes of a one-wave workgroup of NV values per lane,
 // through LDS instead of a butterfly of compensated merges (which costs NV
 // merges per stage and lane). On entry lds[v * 64 + lane] holds lane's value
