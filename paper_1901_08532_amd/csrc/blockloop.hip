@@ -194,16 +194,21 @@ __device__ __forceinline__ int fin_seg(int split) {
     return seg;
 }
 // Waves per target in the wide finishing reduction (split > kFinSplitNarrow):
-// the power of two covering the slices in 256s, at most the workgroup's 8.
-__device__ __forceinline__ int fin_wpt(int split) {
+// the power of two covering the slices in 256s, at most the workgroup's 8;
+// a block that fits one round with waves to spare spreads each target's
+// slices over more waves (shorter per-lane sum chains, down to 4 slices
+// per lane).
+__device__ __forceinline__ int fin_wpt(int split, int n_act) {
+    constexpr int kWaves = kFinThreads / 64;
     int w = 1;
-    while (256 * w < split && w < kFinThreads / 64) w <<= 1;
+    while (256 * w < split && w < kWaves) w <<= 1;
+    while (w < kWaves && kWaves / (2 * w) >= n_act && split >= 4 * kFinGroups * 2 * w) w <<= 1;
     return w;
 }
 // Targets per finishing workgroup round: kFinThreads / seg with few slices,
 // 8 / fin_wpt with more.
-__device__ __forceinline__ int fin_per_round(int split) {
-    return split > kFinSplitNarrow ? kFinThreads / 64 / fin_wpt(split)
+__device__ __forceinline__ int fin_per_round(int split, int n_act) {
+    return split > kFinSplitNarrow ? kFinThreads / 64 / fin_wpt(split, n_act)
                                    : kFinThreads / fin_seg(split);
 }
 // Evaluation shape for n_act targets, chosen by one wave (every lane calls
@@ -269,7 +274,8 @@ __device__ int launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsign
             cost += (float)sp * (float)n_act / (2400.0f * ipl);
             // the finishing kernel's rounds, each about 10 us (42 rows of a
             // 64-target unit)
-            const float fr = ceilf(ceilf((float)n_act / (float)fin_per_round(sp)) / (float)kFinGrid);
+            const float fr =
+                ceilf(ceilf((float)n_act / (float)fin_per_round(sp, n_act)) / (float)kFinGrid);
             cost += fr * 42.0f / ipl;
             // XCD-aligned slices win within 2% (fewer source re-reads)
             if (lane < 8 && (sp & 7) == 0) cost *= 0.98f;
@@ -294,7 +300,7 @@ __device__ int launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsign
 }
 
 __device__ __forceinline__ int fin_workers(int n_act, int split) {
-    const int w = cdiv32(n_act, fin_per_round(split));
+    const int w = cdiv32(n_act, fin_per_round(split, n_act));
     return w < kFinGrid ? w : kFinGrid;
 }
 
@@ -786,7 +792,7 @@ __device__ __forceinline__ void predict_rest(const LoopArgs &A, int L0, int64_t 
 }
 
 // Compensated slice sums, corrector, list updates, and (last workgroup) the
-// plan of the next block. Targets go in rounds of fin_per_round(split):
+// plan of the next block. Targets go in rounds of fin_per_round(split, n_act):
 // with few slices seg threads per target, four slices each (the slice sums
 // stored target-minor, so the loads are coalesced), merged in order; with more,
 // one wave per target whose lanes are (component, group) -- 9 x 7 -- each
@@ -839,7 +845,7 @@ __global__ __launch_bounds__(kFinThreads) void k_bl_finish(LoopArgs A, int64_t s
     const int64_t t_spec = tn + ((int64_t)1 << (kTickBits - h.lv_hi));
     const int split = h.split;
     const bool wide = split > kFinSplitNarrow;
-    const int per = fin_per_round(split);
+    const int per = fin_per_round(split, n_act);
     const int workers = fin_workers(n_act, split);
     if ((int)blockIdx.x >= workers) {
         // no targets: the particles not due, to t_spec
