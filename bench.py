@@ -132,12 +132,14 @@ def main():
     ap.add_argument("--seed", type=int, default=None,
                     help="initial-condition seed (default 2; 4 for the adjoint workload)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
-    ap.add_argument("--workload", choices=("plummer", "plummer-imf", "two-clusters", "adjoint"),
+    ap.add_argument("--workload", choices=("plummer", "plummer-imf", "two-clusters", "adjoint",
+                                           "adjoint-block"),
                     default="plummer",
                     help="equal-mass Plummer sphere; Plummer with dN/dm ~ m^-2.35 masses "
                          "(mass seed 10*seed+seed); two Plummer spheres of n/2 on a head-on "
                          "approach (seeds seed, 10*seed+seed); adjoint: gradient of a loss on "
-                         "the final positions of 64 shared steps (one step = forward + backward)")
+                         "the final positions of 64 shared steps (one step = forward + backward); "
+                         "adjoint-block: the same loss through 1/16 time unit of block steps")
     ap.add_argument("--accuracy-targets", type=int, default=256,
                     help="sampled targets of the last block checked against the FP64 oracle")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -179,6 +181,8 @@ def main():
         del src, dst
     if args.workload == "adjoint":
         return run_adjoint(args)
+    if args.workload == "adjoint-block":
+        return run_adjoint_block(args)
     args.n = 65536 if args.n is None else args.n
     args.seed = 2 if args.seed is None else args.seed
     n, eps, eta, lev_min, lev_max = args.n, 1e-4, 0.4, 4, 30
@@ -640,6 +644,100 @@ def _vjp_traffic_per_launch():
     rec = _vjp_record()
     key = "hbm_bytes_per_launch_eval_vjp"
     return float(rec[key]) if rec and key in rec else None
+
+
+def run_adjoint_block(args):
+    """Block-step adjoint workload: Plummer N = 16384, eps = 1e-3, start-up
+    then every block step to 1/16 time unit (eta 0.4, levels 4..30), loss
+    and targets as the shared-step adjoint workload. One bench step is one
+    loss evaluation plus its full gradient with respect to the initial
+    positions, velocities and masses, the step lengths held fixed (forward
+    blocks, then the backward pass: segment replay from the checkpoints and
+    the transposes of each block's corrector, active-set evaluation and
+    predictor). value counts, per bench step, the forward blocks' pair
+    interactions (sum of N_act N) and the VJP's (twice that: the active
+    targets against all sources and every source against the active
+    targets); the replay inside the backward pass is not counted. The
+    block sequence's active counts come from the same start-up run through
+    the host loop (the same kernels, the same blocks)."""
+    import numpy as np
+    import torch
+
+    from paper_1901_08532_amd import h6, ics
+    from paper_1901_08532_amd.adjoint import hermite_block_run
+
+    n = 16384 if args.n is None else args.n
+    seed = 4 if args.seed is None else args.seed
+    eps, eta, lev_min, lev_max = 1e-3, 0.4, 4, 30
+    t_end = 1 << (h6.TICK_BITS - lev_min)
+    torch.cuda.set_device(0)
+    _log("inputs: adjoint-block plummer N=%d seed=%d" % (n, seed))
+    x, v, m = ics.plummer(n, seed)
+    rng = np.random.Generator(np.random.PCG64(10 * seed + seed))
+    xt = x + 0.01 * rng.normal(0, 1, (n, 3))
+    probe = h6.System(x, v, m, eps)
+    probe.startup(eta_s=0.1, lev_min=lev_min, lev_max=lev_max)
+    rc, st = probe.run_blocks(t_end, eta, lev_min, lev_max, host_loop=True, check=False)
+    if rc not in (h6.H6_OK, h6.H6_EDTMIN):
+        raise h6.H6Error(rc, "block sequence")
+    del probe
+    ctx = h6.Context(n, eps)
+    X0, V0, M0, XT = (torch.from_numpy(a).cuda() for a in (x, v, m, xt))
+
+    def forward():
+        with torch.no_grad():
+            return hermite_block_run(X0, V0, M0, ctx, t_end, eta, lev_min, lev_max)
+
+    def one():
+        x0, v0, m0 = (a.clone().requires_grad_(True) for a in (X0, V0, M0))
+        xT, _ = hermite_block_run(x0, v0, m0, ctx, t_end, eta, lev_min, lev_max)
+        loss = ((xT - XT) ** 2).sum()
+        return loss.detach(), torch.autograd.grad(loss, (x0, v0, m0))
+
+    for w in range(args.warmup):
+        one()
+        torch.cuda.synchronize()
+        _log("warmup step %d done" % w)
+    reps = max(1, args.steps // 4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        forward()
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss, grads = one()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    finite = all(bool(torch.isfinite(g).all()) for g in grads) and bool(torch.isfinite(loss))
+    pairs = float(st.particle_steps) * n
+    value = args.steps * 3.0 * pairs / wall
+    out = {
+        "metric": "block-step pair interactions per second, forward blocks and their VJPs",
+        "value": value,
+        "unit": "pair interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / max(1, args.steps),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "plummer_n%d_eps1e-3_seed%d_blocksteps_eta0.4_1/16tu_adjoint" % (n, seed),
+                   "n": n, "eps": eps, "eta": eta, "lev_min": lev_min, "lev_max": lev_max,
+                   "time_units": 1.0 / 16},
+        "blocks": st.blocks,
+        "particle_steps": st.particle_steps,
+        "forward_s": t_fwd,
+        "gradient_s": wall / max(1, args.steps),
+        "gradient_over_forward": (wall / max(1, args.steps)) / t_fwd if t_fwd > 0 else None,
+        "gradient_finite": finite,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def run_adjoint(args):

@@ -20,7 +20,7 @@ def test_workload_choices_include_adjoint():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 0
-    for w in ("plummer", "plummer-imf", "two-clusters", "adjoint"):
+    for w in ("plummer", "plummer-imf", "two-clusters", "adjoint", "adjoint-block"):
         assert w in r.stdout
     assert "--accuracy-targets" in r.stdout
 
