@@ -222,7 +222,9 @@ def main():
         _log("warmup step %d: %d blocks" % (w, st.blocks))
     sysg.S.copy_(S0)
     sysg.T.copy_(T0)
-    sysg.ctx.h6_profile_enable(True)
+    # both kernels of every slot timed: each dispatch carries one event, at
+    # its end, so timing the finishing kernels too costs nothing more
+    sysg.ctx.h6_profile_enable(2)
     torch.cuda.synchronize()
 
     blocks = psteps = 0
@@ -246,7 +248,7 @@ def main():
 
     # per instantiation (summed over active-set bins) and per active-set bin;
     # bin -1 holds the evaluation launches of empty blocks (device loop)
-    evals = [p for p in prof if p["order"] == 2]
+    evals = [p for p in prof if p["order"] == 2 and p["kind"] != 4]  # not the finishing kernel
     inst = {}
     bins = {}
     empty_launches = 0
@@ -306,7 +308,9 @@ def main():
         roofline["executed_flops_per_interaction"] = xfl
         roofline["executed_tflops"] = achieved * xfl / FLOPS_PER_INTERACTION
 
-    acc = timings = cpu = step_roofs = mixed = None
+    # the two kernels of every block over the timed window
+    step_roofs = None if args.host_loop else _loop_breakdown(prof, blocks, prec)
+    acc = timings = cpu = mixed = None
     if not args.timed_only:
         # accuracy of the timed kernel itself: one more sync interval of the
         # same loop (untimed), whose last block (every particle active)
@@ -376,12 +380,6 @@ def main():
                           "of the final synchronised state (%.1f s)" % (n_i, n, tc),
             }
             _log("cpu baseline: %.3e interactions/s on %d threads" % (cpu["value"], cpu["cores"]))
-
-        # the two kernels of every block, timed over the first sync interval
-        # again (untimed: events on every dispatch cost wall time)
-        sysg.S.copy_(S0)
-        sysg.T.copy_(T0)
-        step_roofs = _loop_breakdown(sysg, sync_ticks, eta, lev_min, lev_max, prec)
 
         if not args.no_mixed:
             mixed = _mixed_vs_fp64(args, h6, ics, oracle)
@@ -492,22 +490,17 @@ def _loop_accuracy(sysg, t_end, eta, lev_min, lev_max, prec, m, eps, n_targets, 
     return acc
 
 
-def _loop_breakdown(sysg, sync_ticks, eta, lev_min, lev_max, prec):
-    """One sync interval with the evaluation and finishing kernels of every
-    block event-timed (profile level 2; the finishing kernels of the
+def _loop_breakdown(recs, blocks, prec):
+    """The evaluation and finishing kernels of every block over the timed
+    window (profile level 2 records; the finishing kernels of the
     prediction slots apart, their evaluations are empty): launches, time,
     algorithmic bytes (each datum moved once, from the block's active count
     and slice count) and the resulting fraction of the 8 TB/s HBM bound
-    per kernel. The events add about 3 us to each dispatch's measured time,
-    which dominates the smallest blocks' kernels."""
+    per kernel. A dispatch is timed from the end of the one before it, so
+    its launch latency (a few microseconds) is in its time, which dominates
+    the smallest blocks' kernels."""
     from paper_1901_08532_amd import h6
 
-    sysg.ctx.h6_profile_enable(2)
-    rc, stats = sysg.run_blocks(sync_ticks, eta, lev_min, lev_max, prec, check=False)
-    recs = sysg.ctx.h6_profile_read()
-    sysg.ctx.h6_profile_enable(False)
-    if rc != h6.H6_OK:
-        raise h6.H6Error(rc, "h6_run_blocks (breakdown)")
     names = {2: "k_bl_eval", 4: "k_bl_finish", -4: "k_bl_finish (prediction slots)"}
     agg = {k: {"launches": 0, "kernel_ms": 0.0, "bytes": 0.0} for k in names}
     for r in recs:
@@ -521,7 +514,7 @@ def _loop_breakdown(sysg, sync_ticks, eta, lev_min, lev_max, prec):
         a["kernel_ms"] += r["kernel_ms"]
         a["bytes"] += r["bytes"]
     total_ms = sum(a["kernel_ms"] for a in agg.values())
-    out = {"interval_blocks": stats.blocks, "window": "the first sync interval, events on every dispatch"}
+    out = {"blocks": blocks, "window": "the timed window, an end event on every dispatch"}
     for k, name in names.items():
         a = agg[k]
         secs = a["kernel_ms"] * 1e-3

@@ -432,9 +432,13 @@ int h6_energy_vjp(h6_ctx ctx, const h6_state *st, int64_t n, const double *cot_e
  * Measurement hook: while enabled (on = 1), HIP events bracket every a/j/s
  * evaluation kernel the context launches (on its stream), and the event
  * durations are accumulated per kernel instantiation and per power-of-two
- * bin of the active-set size. on = 2 also times the device-resident loop's
- * finishing kernel of every block (records of kind 4, binned by the block's
- * active count like its evaluation). on = 3 records no events (nothing is
+ * bin of the active-set size. In the device-resident loop both dispatches
+ * of a slot carry one event each, at their end (part of the dispatch: no
+ * marker packet in the stream), and a dispatch is timed from the end of
+ * the work before it on the stream (the other kernel, the loop's start or
+ * a plan readback), launch latency included. on = 2 also reports the
+ * loop's finishing kernel of every block (records of kind 4, binned by the
+ * block's active count like its evaluation). on = 3 records no events (nothing is
  * added to the dispatches, for an external tracer) and keeps only the
  * device-resident loop's slot log. on = 0 turns the hook off. Enabling
  * clears the records. h6_profile_read (synchronizes) copies up to max

@@ -154,18 +154,23 @@ static double eval_bytes(double n_src, double n_act, int split) {
     return 80.0 * n_src + n_act * (76.0 + kSliceBytes * (split > 1 ? split : 0));
 }
 
-hipError_t prof_events(h6_ctx ctx, hipEvent_t *e0, hipEvent_t *e1) {
-    for (hipEvent_t *e : {e0, e1}) {
-        if (!ctx->event_pool.empty()) {
-            *e = ctx->event_pool.back();
-            ctx->event_pool.pop_back();
-        } else {
-            // timestamps only: no system-scope cache flush at the marker
-            hipError_t r = hipEventCreateWithFlags(e, hipEventDisableSystemFence);
-            if (r != hipSuccess) return r;
-        }
+// A timing event from the pool, held until the next resolve.
+hipError_t prof_event(h6_ctx ctx, hipEvent_t *e) {
+    if (!ctx->event_pool.empty()) {
+        *e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+    } else {
+        // timestamps only: no system-scope cache flush at the marker
+        hipError_t r = hipEventCreateWithFlags(e, hipEventDisableSystemFence);
+        if (r != hipSuccess) return r;
     }
+    ctx->prof_held.push_back(*e);
     return hipSuccess;
+}
+
+hipError_t prof_events(h6_ctx ctx, hipEvent_t *e0, hipEvent_t *e1) {
+    hipError_t r = prof_event(ctx, e0);
+    return r != hipSuccess ? r : prof_event(ctx, e1);
 }
 
 hipError_t prof_begin(h6_ctx ctx, hipEvent_t *e0, hipEvent_t *e1) {
@@ -251,10 +256,14 @@ hipError_t prof_resolve(h6_ctx ctx) {
         t.interactions += inter;
         t.kernel_ms += ms;
         t.bytes += bytes;
-        ctx->event_pool.push_back(p.e0);
-        ctx->event_pool.push_back(p.e1);
     }
     ctx->pending.clear();
+    // every event back to the pool but the device loop's current mark,
+    // which the next evaluation's timing starts from
+    for (hipEvent_t e : ctx->prof_held)
+        if (e != ctx->bl_mark) ctx->event_pool.push_back(e);
+    ctx->prof_held.clear();
+    if (ctx->bl_mark) ctx->prof_held.push_back(ctx->bl_mark);
     return hipSuccess;
 }
 
@@ -347,10 +356,7 @@ int h6_destroy(h6_ctx ctx) {
     if (ctx->bl_log) (void)hipFree(ctx->bl_log);
     for (hipEvent_t e : ctx->bl_ev)
         if (e) (void)hipEventDestroy(e);
-    for (const auto &p : ctx->pending) {
-        (void)hipEventDestroy(p.e0);
-        (void)hipEventDestroy(p.e1);
-    }
+    for (hipEvent_t e : ctx->prof_held) (void)hipEventDestroy(e);  // the pending timings' events
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
     delete ctx;
     return H6_OK;
@@ -659,6 +665,13 @@ static int run_blocks_device(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred 
         const int64_t r = ((t_end - p.t_next) >> (kTickBits - p.lv_hi)) + 1;
         return r + r / 16 + 1;
     };
+    // measurement hook: each loop dispatch carries one event, at its end; an
+    // evaluation's span starts at the mark (the end of the dispatch or copy
+    // before it)
+    if (ctx->prof) {
+        H6_TRY(ctx, prof_event(ctx, &ctx->bl_mark), "profile event");
+        H6_TRY(ctx, hipEventRecord(ctx->bl_mark, ctx->stream), "event record");
+    }
     int64_t seq = 0;
     int next = 0;               // readback slot of the next batch
     int last = 0;               // readback slot enqueued last (0: the set-up plan)
@@ -687,6 +700,10 @@ static int run_blocks_device(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred 
                               hipMemcpyDeviceToHost, ctx->stream),
                "block status readback");
         H6_TRY(ctx, hipEventRecord(ctx->bl_ev[next], ctx->stream), "event record");
+        if (ctx->prof) {
+            H6_TRY(ctx, prof_event(ctx, &ctx->bl_mark), "profile event");
+            H6_TRY(ctx, hipEventRecord(ctx->bl_mark, ctx->stream), "event record");
+        }
         last = next;
         if (pending) {
             H6_TRY(ctx, hipEventSynchronize(ctx->bl_ev[pend]), "event wait");
@@ -708,6 +725,7 @@ static int run_blocks_device(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred 
     ctx->bl_slots = seq;
     // the copy enqueued last (or the set-up plan when nothing was due)
     const LoopDesc &d = *slot[last];
+    ctx->bl_mark = nullptr;  // returned to the pool by the next resolve
     if (!ctx->pending.empty()) H6_TRY(ctx, prof_resolve(ctx), "profile events");
     if (stats) {
         stats->blocks = d.blocks;

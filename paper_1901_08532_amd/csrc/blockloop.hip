@@ -990,37 +990,37 @@ hipError_t bl_setup(h6_ctx ctx, const LoopArgs &A) {
 }
 
 hipError_t bl_enqueue_block(h6_ctx ctx, const LoopArgs &A, int precision, int64_t seq) {
-    // with the measurement hook on, the events are those of the dispatches
-    // themselves (no separate marker packets in the stream)
-    const bool all = ctx->prof && ctx->prof_level >= 2;
-    auto events = [&](hipEvent_t *e0, hipEvent_t *e1, bool on) {
-        *e0 = *e1 = nullptr;
-        return on ? prof_events(ctx, e0, e1) : hipSuccess;
+    // with the measurement hook on, both dispatches carry an end event (part
+    // of the dispatch itself: no marker packet in the stream); a dispatch's
+    // span runs from the end of the work before it (ctx->bl_mark)
+    const bool prof = ctx->prof;
+    hipEvent_t ev_eval = nullptr, ev_fin = nullptr;
+    hipError_t pe = hipSuccess;
+    if (prof && ((pe = prof_event(ctx, &ev_eval)) != hipSuccess ||
+                 (pe = prof_event(ctx, &ev_fin)) != hipSuccess))
+        return pe;
+    auto push = [&](hipEvent_t e0, hipEvent_t e1, int kind) {
+        hipError_t r = hipGetLastError();
+        return r != hipSuccess ? r : prof_push_seq(ctx, e0, e1, precision, seq, kind);
     };
-    auto push = [&](hipEvent_t e0, hipEvent_t e1, bool on, int kind) {
-        if (!on) return hipSuccess;
-        hipError_t pe = hipGetLastError();
-        return pe != hipSuccess ? pe : prof_push_seq(ctx, e0, e1, precision, seq, kind);
-    };
-    hipEvent_t ev0, ev1;
-    hipError_t pe = events(&ev0, &ev1, ctx->prof);
-    if (pe != hipSuccess) return pe;
     const bool skip = self_pair_masked(A.eps2, precision);
     const bool mixed = precision == H6_MIXED;
-#define H6_BL_EVAL(M, S)                                                                         \
-    hipExtLaunchKernelGGL((k_bl_eval<M, S>), dim3(A.eval_grid), dim3(64), 0, ctx->stream, ev0, \
-                          ev1, 0u, A, seq)
+#define H6_BL_EVAL(M, S)                                                                    \
+    hipExtLaunchKernelGGL((k_bl_eval<M, S>), dim3(A.eval_grid), dim3(64), 0, ctx->stream, \
+                          nullptr, ev_eval, 0u, A, seq)
     if (mixed) {
         if (skip) H6_BL_EVAL(true, true); else H6_BL_EVAL(true, false);
     } else {
         if (skip) H6_BL_EVAL(false, true); else H6_BL_EVAL(false, false);
     }
 #undef H6_BL_EVAL
-    if ((pe = push(ev0, ev1, ctx->prof, 2)) != hipSuccess) return pe;
-    if ((pe = events(&ev0, &ev1, all)) != hipSuccess) return pe;
-    hipExtLaunchKernelGGL(k_bl_finish, dim3(kFinLaunch), dim3(kFinThreads), 0, ctx->stream, ev0,
-                          ev1, 0u, A, seq);
-    if ((pe = push(ev0, ev1, all, 4)) != hipSuccess) return pe;
+    if (prof && (pe = push(ctx->bl_mark, ev_eval, 2)) != hipSuccess) return pe;
+    hipExtLaunchKernelGGL(k_bl_finish, dim3(kFinLaunch), dim3(kFinThreads), 0, ctx->stream,
+                          nullptr, ev_fin, 0u, A, seq);
+    if (prof) {
+        if (ctx->prof_level >= 2 && (pe = push(ev_eval, ev_fin, 4)) != hipSuccess) return pe;
+        ctx->bl_mark = ev_fin;
+    }
     return hipGetLastError();
 }
 

@@ -172,6 +172,9 @@ struct h6_ctx_s {
                          // 3: no events, the device loop's slot log only
     int64_t bl_slots = 0;  // slots the last device-loop run enqueued (slot log)
     std::vector<hipEvent_t> event_pool;
+    std::vector<hipEvent_t> prof_held;  // events of the pending timings (back to the pool on resolve)
+    hipEvent_t bl_mark = nullptr;  // device loop: the end of the stream's work before the next
+                                   // evaluation (held across resolves)
     std::vector<PendingTiming> pending;
     std::vector<h6_eval_timing> timings;
 };
@@ -236,6 +239,7 @@ int sched_blocks_for(int64_t n);
 // launch that records them itself (hipExtLaunchKernel), prof_push_seq
 // queues such a pair for a device-loop block.
 hipError_t prof_events(h6_ctx ctx, hipEvent_t *e0, hipEvent_t *e1);
+hipError_t prof_event(h6_ctx ctx, hipEvent_t *e);
 hipError_t prof_begin(h6_ctx ctx, hipEvent_t *e0, hipEvent_t *e1);
 hipError_t prof_end(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int order, const EvalConfig &cfg,
                     int precision, int64_t n_act, double interactions);
