@@ -181,6 +181,37 @@ def test_device_loop_profile_records_of_both_kernels():
     assert by_kind[2][2] >= 80.0 * n * st.blocks + 76.0 * st.particle_steps
 
 
+def test_device_loop_end_events_across_runs():
+    # level 2 over two consecutive runs: each loop dispatch carries one event,
+    # at its end, and is timed from the end of the work before it (the other
+    # kernel, the run's start or a plan readback). Every block of both runs
+    # is timed once per kernel with a positive span, and the spans, which
+    # tile the stream's time without overlapping, sum to no more than the
+    # wall time of the two runs
+    import time
+
+    n = 8192
+    x, v, m = ics.plummer(n, 14)
+    s = h6.System(x, v, m, EPS)
+    s.startup(eta_s=0.1, lev_min=4, lev_max=30)
+    s.ctx.h6_profile_enable(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc1, st1 = s.run_blocks(SYNC // 2, 0.4, 4, 30)
+    rc2, st2 = s.run_blocks(SYNC, 0.4, 4, 30)
+    torch.cuda.synchronize()
+    wall_ms = 1e3 * (time.perf_counter() - t0)
+    recs = s.ctx.h6_profile_read()
+    s.ctx.h6_profile_enable(False)
+    assert rc1 == rc2 == h6.H6_OK and st1.blocks > 0 and st2.blocks > 0
+    loop = [r for r in recs if r["kind"] in (2, 4)]
+    for kind in (2, 4):
+        real = [r for r in loop if r["kind"] == kind and r["nact_log2"] >= 0]
+        assert sum(r["launches"] for r in real) == st1.blocks + st2.blocks, kind
+        assert all(r["kernel_ms"] > 0 for r in real), kind
+    assert sum(r["kernel_ms"] for r in loop) <= wall_ms
+
+
 def test_slot_log_accounts_for_every_block():
     # profile level 3: no events, the slot log only. Every block appears once
     # with its active count, prediction slots carry the count of the block
