@@ -118,6 +118,7 @@ class _HermiteBlockRun(torch.autograd.Function):
         lib_ctx.h6_initial_steps(S, mm, T, eta_s, lev_min, lev_max)
         S0 = S.clone()
         ckpts = []
+        seq = []  # the block sequence: (time, active count, active particles)
         blocks = 0
         while True:
             tn, na = lib_ctx.h6_next_block(S, mm, T, act)
@@ -125,6 +126,7 @@ class _HermiteBlockRun(torch.autograd.Function):
                 break
             if blocks % checkpoint == 0:
                 ckpts.append((S.clone(), T.clone()))
+            seq.append((tn, na, act[:na].clone()))
             _block(lib_ctx, S, mm, T, P, F, act, tn, na, eta, lev_min, lev_max)
             blocks += 1
         rc = lib_ctx.h6_check_status()
@@ -133,6 +135,7 @@ class _HermiteBlockRun(torch.autograd.Function):
         ctx.lib_ctx = lib_ctx
         ctx.params = (eta, lev_min, lev_max, checkpoint, blocks)
         ctx.ckpts = ckpts
+        ctx.seq = seq
         ctx.S0 = S0
         ctx.save_for_backward(mm)
         return S[0:3].T.contiguous(), S[3:6].T.contiguous()
@@ -151,17 +154,17 @@ class _HermiteBlockRun(torch.autograd.Function):
         F = torch.empty((9, n), dtype=torch.float64, device=dev)
         CF = torch.empty((9, n), dtype=torch.float64, device=dev)
         CP = torch.empty((9, n), dtype=torch.float64, device=dev)
-        act = torch.empty(n, dtype=torch.int32, device=dev)
         for seg in reversed(range(len(ctx.ckpts))):
+            # replay the segment from its checkpoint along the recorded block
+            # sequence (the same kernels: the same values), with no host
+            # round trip per block
             S, T = (t.clone() for t in ctx.ckpts[seg])
-            count = min(k, blocks - seg * k)
             recs = []
-            for _ in range(count):
+            for tn, na, a_idx in ctx.seq[seg * k: min(blocks, (seg + 1) * k)]:
                 T_old = T.clone()
-                tn, na = lc.h6_next_block(S, mm, T, act)
                 P = torch.empty((9, n), dtype=torch.float64, device=dev)
-                _block(lc, S, mm, T, P, F, act, tn, na, eta, lev_min, lev_max)
-                recs.append((tn, na, act[:na].clone(), T_old, P))
+                _block(lc, S, mm, T, P, F, a_idx, tn, na, eta, lev_min, lev_max)
+                recs.append((tn, na, a_idx, T_old, P))
             for tn, na, a_idx, T_old, P in reversed(recs):
                 lc.h6_correct_vjp(cot, gm, a_idx, na, T_old[1], CF)
                 CP.zero_()
@@ -191,9 +194,10 @@ def hermite_block_run(x0, v0, m, lib_ctx: h6.Context, t_end_ticks: int, eta: flo
     Steps: initial ones from the 4th-order criterion (eta_s), then the
     6th-order block rule (eta, levels lev_min..lev_max), as h6_block_step.
     The gradient treats every step length as fixed. The forward pass keeps
-    the state every `checkpoint` blocks; the backward pass replays each
-    segment from its checkpoint (the same kernels, so the same block
-    sequence and values) and reverses its blocks.
+    the state every `checkpoint` blocks and the block sequence (each block's
+    time and active particles); the backward pass replays each segment from
+    its checkpoint along that sequence (the same kernels, so the same
+    values, and no host round trip per block) and reverses its blocks.
     """
     if checkpoint < 1:
         raise ValueError("checkpoint must be >= 1")
