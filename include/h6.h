@@ -65,7 +65,8 @@ enum {
  * predictor, corrector and step rule are FP64 in every case. */
 enum {
     H6_FP64 = 0,  /* all pair arithmetic and sums in IEEE double */
-    H6_MIXED = 1, /* double differences and accumulators, float pair math */
+    H6_MIXED = 1, /* double position and velocity differences and accumulators,
+                     float pair math */
     H6_EX = 2,    /* double-single ("float-float") pair arithmetic and
                      per-slice sums, float operations only */
     H6_SP = 3     /* single-precision pair arithmetic and per-slice sums */
