@@ -11,8 +11,9 @@
 //   * acceleration differences, the reciprocal square root (v_rsq_f32 and
 //     one Newton step), alpha, beta and the pair terms are FP32;
 //   * the a/j/s sums are FP64: FP32 products are gathered over 8 sources,
-//     then added to FP64 accumulators, which are flushed into compensated
-//     (hi, lo) pairs once per tile as in the FP64 kernel.
+//     then added to FP64 accumulators; the tiled body adds them plainly
+//     (the FP64 rounding, about 1e-16 per addition, stays far below the
+//     FP32 terms' own), the source-parallel body into compensated pairs.
 // The launch structure (LDS tiles of sources, target per lane, source
 // slices, separate compensated slice reduction) is the FP64 kernel's.
 #include "eval_mixed_body.h"

@@ -89,11 +89,14 @@ __device__ __forceinline__ void mixed_tile_body(const SRC &S, int n, int n_act, 
 #pragma unroll
         for (int c = 0; c < 3; ++c) ai[u][c] = (float)ad[c];
     }
-    double acc[IPL][9], hi[IPL][9], lo[IPL][9];
+    // FP64 sums of the FP32 chunk sums, uncompensated: their rounding (about
+    // 1e-16 relative per addition) stays orders of magnitude below the
+    // FP32 pair terms' own (about 6e-8)
+    double acc[IPL][9];
 #pragma unroll
     for (int u = 0; u < IPL; ++u)
 #pragma unroll
-        for (int q = 0; q < 9; ++q) acc[u][q] = hi[u][q] = lo[u][q] = 0.0;
+        for (int q = 0; q < 9; ++q) acc[u][q] = 0.0;
 
     const int jb = sl * slice_len;
     const int je = min(n, jb + slice_len);
@@ -152,20 +155,13 @@ __device__ __forceinline__ void mixed_tile_body(const SRC &S, int n, int n_act, 
 #pragma unroll
                 for (int q = 0; q < 9; ++q) acc[u][q] += (double)acc32[u][q];
         }
-#pragma unroll
-        for (int u = 0; u < IPL; ++u)
-#pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                two_sum_into(hi[u][q], lo[u][q], acc[u][q]);
-                acc[u][q] = 0.0;
-            }
     }
     const int64_t soff = (int64_t)sl * slice_stride;
 #pragma unroll
     for (int u = 0; u < IPL; ++u)
         if (kid[u] < n_act)
 #pragma unroll
-            for (int q = 0; q < 9; ++q) out.p[q][soff + kid[u] * out.kstride] = hi[u][q] + lo[u][q];
+            for (int q = 0; q < 9; ++q) out.p[q][soff + kid[u] * out.kstride] = acc[u][q];
 }
 
 // Small active sets: lanes over sources, TPW targets per wave (as the FP64
