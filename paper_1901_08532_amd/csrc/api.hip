@@ -639,7 +639,8 @@ static int run_blocks_device(h6_ctx ctx, h6_state *st, int64_t n, const h6_pred 
     A.lev_min = prm->lev_min;
     A.lev_max = prm->lev_max;
     A.t_end = t_end;
-    A.eval_grid = bl_eval_grid(ctx);
+    A.eval_grid = bl_eval_grid(ctx, prm->precision);
+    A.one_target_small = prm->precision == H6_MIXED ? 1 : 0;
     A.pc_pairs = (unsigned)(ctx->partial_cap / 9);
     A.flags = ctx->flags;
     A.nact_log = ctx->prof_level > 0 ? ctx->bl_log : nullptr;

@@ -214,10 +214,11 @@ __device__ __forceinline__ int fin_per_round(int split, int n_act) {
 // Evaluation shape for n_act targets, chosen by one wave (every lane calls
 // it, lane 0 writes *d; every lane gets the slice count back).
 // Source-parallel kinds (1: one target per wave, 3: two): slices of at least
-// 256 sources (4 per lane), at most eval_grid waves in all. Tile kinds: kind 2 (up to kTile1Max targets) has 64 targets per one-wave
+// 256 sources, at most eval_grid waves in all (the mixed form one target
+// per wave only, which keeps its kernel within four waves' registers). Tile kinds: kind 2 (up to kTile1Max targets) has 64 targets per one-wave
 // workgroup (one per lane), kind 0 128 (two per lane). The grid holds two
-// waves per SIMD, which share its issue rate, so a round of units is one
-// unit per SIMD. For a tile kind lanes r - 1 and r + 7 (r = 1..8) price
+// waves per SIMD (the mixed form four, priced as two per half SIMD), which
+// share its issue rate, so a round of units is one unit per SIMD. For a tile kind lanes r - 1 and r + 7 (r = 1..8) price
 // the shape whose units fill r rounds (the first with its slice count
 // rounded as below): the time in source rows of one unit is rounds
 // x slice length (a lone unit per SIMD issuing at about 3/4 of the rate of
@@ -229,12 +230,13 @@ __device__ __forceinline__ int fin_per_round(int split, int n_act) {
 // tile kinds where the price is within 2%: unit g * split + sl then runs on XCD
 // sl mod 8 for every target group g, so each XCD reads one eighth of the
 // sources.
-__device__ int launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, unsigned pc_pairs) {
+__device__ int launch_shape(LoopDesc *d, int n, int n_act, int eval_grid, bool one_small,
+                            unsigned pc_pairs) {
     const int lane = threadIdx.x & 63;
     const int pc = (int)(pc_pairs / (unsigned)n_act) > 0 ? (int)(pc_pairs / (unsigned)n_act) : 1;
     int split, kind, groups, slice;
     if (n_act <= kSmall2Max) {
-        kind = n_act <= kSmall1Max ? 1 : 3;
+        kind = n_act <= kSmall1Max || one_small ? 1 : 3;
         groups = kind == 1 ? n_act : cdiv32(n_act, 2);
         split = (n + 255) >> 8;
         const int fit = eval_grid / groups;
@@ -341,7 +343,7 @@ __device__ void plan_block(const LoopArgs &A, LoopDesc *d, const int *cnt, int64
         for (int l = L; l <= lv_hi; ++l) incl += cnt[l];
     const int n_act = done ? 0 : __builtin_amdgcn_readlane(incl, L0);
     if (act) d->off[L] = incl - c;
-    const int split = done ? 0 : launch_shape(d, A.n, n_act, A.eval_grid, A.pc_pairs);  // the whole wave
+    const int split = done ? 0 : launch_shape(d, A.n, n_act, A.eval_grid, A.one_target_small != 0, A.pc_pairs);  // the whole wave
     if (L != 0) return;
     d->t_next = tn;
     d->lv_hi = lv_hi;
@@ -437,7 +439,7 @@ __device__ __forceinline__ int xcd_slot(int g, int sl, int split) {
 }
 
 template <bool MIXED, bool SKIPSELF>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_bl_eval(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MIXED ? 4 : 2))) void k_bl_eval(
     LoopArgs A, int64_t seq) {
     const LoopDesc *__restrict__ d = A.desc + (seq & 1);
     const DescHead h = load_head(d);
@@ -511,19 +513,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
             const int g = u / split, sl = u - g * split;
             const OutPtrs o = out_of(g, sl);
             if (kind == 1) {
+                // mixed: two sources per lane in flight, so that the kernel
+                // fits the registers of four waves per SIMD
                 if constexpr (MIXED)
-                    mixed_small_body<1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, o,
-                                                  slice_stride, g, sl, red);
+                    mixed_small_body<1, SKIPSELF, 2>(S, A.n, n_act, A.eps2, slice_len, o,
+                                                     slice_stride, g, sl, red);
                 else
                     eval_small_body<1, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, o,
                                                  slice_stride, g, sl, red);
             } else {
-                if constexpr (MIXED)
-                    mixed_small_body<2, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, o,
-                                                  slice_stride, g, sl, red);
-                else
+                // two targets per wave: FP64 only (the mixed plan takes one)
+                if constexpr (MIXED) {
+                    if (threadIdx.x == 0) atomicOr(A.flags, kFlagLoop);
+                } else {
                     eval_small_body<2, SKIPSELF>(S, A.n, n_act, A.eps2, slice_len, o,
                                                  slice_stride, g, sl, red);
+                }
             }
         }
     }
@@ -977,7 +982,11 @@ __global__ void k_bl_setup_plan(LoopArgs A) {
 
 }  // namespace
 
-int bl_eval_grid(h6_ctx ctx) { return ctx->n_cu * 8; }  // one round of resident tile workgroups
+// One round of resident evaluation workgroups (one wave each): two per SIMD,
+// four for the mixed form, whose evaluation kernel fits their registers.
+int bl_eval_grid(h6_ctx ctx, int precision) {
+    return ctx->n_cu * (precision == H6_MIXED ? 16 : 8);
+}
 
 int64_t bl_list_ints(int64_t n, int nl) { return 2 * (int64_t)nl * n + (2 * n + 3) / 4; }
 

@@ -253,9 +253,12 @@ EvalConfig choose_eval_config(h6_ctx ctx, int order, int precision, int n, int n
         split = ctx->cfg_split;
     } else {
         // measured footprints on gfx950: order 2 with one target per lane
-        // <= 128 VGPRs (4 waves per SIMD), two per lane <= 256 (2 waves);
-        // start-up passes <= 128
-        const int waves_per_simd = (order == 2 && cfg.ipl == 2) ? 2 : 4;
+        // <= 128 VGPRs (4 waves per SIMD), two per lane <= 256 (2 waves),
+        // except the mixed form's (FP32 pair terms, <= 128: 4 waves, and
+        // slices enough to fill them, 8% faster at N = 262144); start-up
+        // passes <= 128
+        const int waves_per_simd =
+            (order == 2 && cfg.ipl == 2 && precision != H6_MIXED) ? 2 : 4;
         split = balanced_split(ctx, waves_per_simd, cfg.block, n, blocks_i);
     }
     const int max_by_tiles = ceil_div(n, cfg.block);

@@ -25,7 +25,7 @@ using namespace mixedbody;
 
 template <int BLOCK, int IPL, bool SKIPSELF>
 __global__ __launch_bounds__(BLOCK)
-__attribute__((amdgpu_waves_per_eu(IPL == 1 ? 4 : 2))) void k_eval_mixed(
+__attribute__((amdgpu_waves_per_eu(4))) void k_eval_mixed(
     SrcPtrs src, const int32_t *__restrict__ active, int n, int n_act, double eps2, int slice_len,
     OutPtrs out, int64_t slice_stride) {
     mixed_tile_body<BLOCK, IPL, SKIPSELF>(src, active, n, n_act, eps2, slice_len, out, slice_stride,

@@ -165,18 +165,19 @@ __device__ __forceinline__ void mixed_tile_body(const SRC &S, int n, int n_act, 
 }
 
 // Small active sets: lanes over sources, TPW targets per wave (as the FP64
-// source-parallel kernel, passes of kPassM sources per lane with their
-// loads issued together), FP32 pair arithmetic, FP32 partial sums over
-// kChunk sources per lane flushed into compensated FP64 pairs.
+// source-parallel kernel, passes of PASS sources per lane with their loads
+// issued together; fewer for a kernel that must fit four waves per SIMD),
+// FP32 pair arithmetic, FP32 partial sums over kChunk sources per lane
+// added to FP64 sums.
 constexpr int kPassM = 4;
 
 // red: 64 * 9 * TPW doubles of workgroup memory (the final reduction).
-template <int TPW, bool SKIPSELF, class SRC>
+template <int TPW, bool SKIPSELF, int PASS = kPassM, class SRC>
 __device__ __forceinline__ void mixed_small_body(const SRC &S, int n, int n_act, double eps2,
                                                  int slice_len, const OutPtrs &out,
                                                  int64_t slice_stride, int wave, int sl,
                                                  double *red) {
-    static_assert(kChunk % kPassM == 0, "flush on pass boundaries");
+    static_assert(kChunk % PASS == 0, "flush on pass boundaries");
     const int lane = threadIdx.x & 63;
     const float eps2f = (float)eps2;
     const int jb = sl * slice_len;
@@ -185,7 +186,7 @@ __device__ __forceinline__ void mixed_small_body(const SRC &S, int n, int n_act,
     // fetched before the targets' (list, then state) loads
     auto load_pass = [&](int jp, double (*xs)[3], double (*vs)[3], float (*as)[3], float *ms) {
 #pragma unroll
-        for (int u = 0; u < kPassM; ++u) {
+        for (int u = 0; u < PASS; ++u) {
             const int j = jp + u * 64 + lane;
             if (j < je) {
                 double ad[3], jd[3];
@@ -204,8 +205,8 @@ __device__ __forceinline__ void mixed_small_body(const SRC &S, int n, int n_act,
             }
         }
     };
-    double xs[kPassM][3], vs[kPassM][3];
-    float as[kPassM][3], ms[kPassM];
+    double xs[PASS][3], vs[PASS][3];
+    float as[PASS][3], ms[PASS];
     load_pass(jb, xs, vs, as, ms);
     double xi[TPW][3], vi[TPW][3];
     float ai[TPW][3];
@@ -221,20 +222,22 @@ __device__ __forceinline__ void mixed_small_body(const SRC &S, int n, int n_act,
 #pragma unroll
         for (int c = 0; c < 3; ++c) ai[t][c] = (float)ad[c];
     }
+    // FP32 sums over kChunk sources per lane, added to plain FP64 sums (as
+    // in the tiled body)
     float acc32[TPW][9];
-    double hi[TPW][9], lo[TPW][9];
+    double acc[TPW][9];
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             acc32[t][q] = 0.0f;
-            hi[t][q] = lo[t][q] = 0.0;
+            acc[t][q] = 0.0;
         }
     int since_flush = 0;
-    for (int jp = jb; jp < je; jp += kPassM * 64) {
+    for (int jp = jb; jp < je; jp += PASS * 64) {
         if (jp != jb) load_pass(jp, xs, vs, as, ms);
 #pragma unroll
-        for (int u = 0; u < kPassM; ++u) {
+        for (int u = 0; u < PASS; ++u) {
             const int j = jp + u * 64 + lane;
 #pragma unroll
             for (int t = 0; t < TPW; ++t) {
@@ -253,14 +256,14 @@ __device__ __forceinline__ void mixed_small_body(const SRC &S, int n, int n_act,
                               m_eff, acc32[t]);
             }
         }
-        since_flush += kPassM;
+        since_flush += PASS;
         if (since_flush == kChunk) {
             since_flush = 0;
 #pragma unroll
             for (int t = 0; t < TPW; ++t)
 #pragma unroll
                 for (int q = 0; q < 9; ++q) {
-                    two_sum_into(hi[t][q], lo[t][q], (double)acc32[t][q]);
+                    acc[t][q] += (double)acc32[t][q];
                     acc32[t][q] = 0.0f;
                 }
         }
@@ -268,10 +271,7 @@ __device__ __forceinline__ void mixed_small_body(const SRC &S, int n, int n_act,
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            two_sum_into(hi[t][q], lo[t][q], (double)acc32[t][q]);
-            red[(t * 9 + q) * 64 + lane] = hi[t][q] + lo[t][q];
-        }
+        for (int q = 0; q < 9; ++q) red[(t * 9 + q) * 64 + lane] = acc[t][q] + (double)acc32[t][q];
     // totals over the lanes: lane t * 9 + q holds component q of target t
     const double total = wave_totals_lds<TPW * 9>(red);
     const int64_t soff = (int64_t)sl * slice_stride;

@@ -111,7 +111,8 @@ struct LoopArgs {
     double eps2, eta6;
     int lev_min, lev_max;
     int64_t t_end;
-    int eval_grid;
+    int eval_grid;        // evaluation workgroups (one wave each): two per SIMD, four mixed
+    int one_target_small; // 1: the source-parallel kinds take one target per wave (mixed)
     unsigned pc_pairs;    // partial capacity / 9: bound on split * n_act
     int32_t *flags;
     int32_t *nact_log;    // (n_act, split) by block sequence number (ring of pairs; split -1:
@@ -248,7 +249,7 @@ hipError_t prof_push_seq(h6_ctx ctx, hipEvent_t e0, hipEvent_t e1, int precision
 hipError_t prof_resolve(h6_ctx ctx);  // stream must be idle
 
 // Device-resident block loop (blockloop.hip).
-int bl_eval_grid(h6_ctx ctx);
+int bl_eval_grid(h6_ctx ctx, int precision);
 int64_t bl_list_ints(int64_t n, int nl);  // list and level-byte storage, n particles, nl levels
 hipError_t bl_setup(h6_ctx ctx, const LoopArgs &A);  // lists and the plan of block 0
 hipError_t bl_enqueue_block(h6_ctx ctx, const LoopArgs &A, int precision, int64_t seq);
