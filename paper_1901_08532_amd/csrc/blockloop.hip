@@ -343,7 +343,10 @@ __device__ void plan_block(const LoopArgs &A, LoopDesc *d, const int *cnt, int64
         for (int l = L; l <= lv_hi; ++l) incl += cnt[l];
     const int n_act = done ? 0 : __builtin_amdgcn_readlane(incl, L0);
     if (act) d->off[L] = incl - c;
-    const int split = done ? 0 : launch_shape(d, A.n, n_act, A.eval_grid, A.one_target_small != 0, A.pc_pairs);  // the whole wave
+    const int split =
+        done ? 0
+             : launch_shape(d, A.n, n_act, A.eval_grid, A.one_target_small != 0,
+                            A.pc_pairs);  // the whole wave
     if (L != 0) return;
     d->t_next = tn;
     d->lv_hi = lv_hi;

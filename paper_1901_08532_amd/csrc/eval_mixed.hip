@@ -11,9 +11,8 @@
 //   * acceleration differences, the reciprocal square root (v_rsq_f32 and
 //     one Newton step), alpha, beta and the pair terms are FP32;
 //   * the a/j/s sums are FP64: FP32 products are gathered over 8 sources,
-//     then added to FP64 accumulators; the tiled body adds them plainly
-//     (the FP64 rounding, about 1e-16 per addition, stays far below the
-//     FP32 terms' own), the source-parallel body into compensated pairs.
+//     then added to plain FP64 accumulators (the FP64 rounding, about 1e-16
+//     per addition, stays far below the FP32 terms' own).
 // The launch structure (LDS tiles of sources, target per lane, source
 // slices, separate compensated slice reduction) is the FP64 kernel's.
 #include "eval_mixed_body.h"
